@@ -1,0 +1,33 @@
+"""Small oracle set-ups shared by the CPU pin tests and the GPU parity tests (oracle side only)."""
+from functools import lru_cache
+
+import numpy as np
+
+from oracle.dg import Operator
+from oracle.mesh import BC_RIGID, BC_TRANSPARENT, OMesh, local_dt, lts_levels
+from oracle.refelem import get_ref
+from paper_1506_00907_amd import inputs as I
+
+
+@lru_cache(maxsize=None)
+def case(name: str, bc: int = BC_TRANSPARENT, n_levels: int = 3):
+    m, rho, c, N = I.config_mesh(name)
+    ref = get_ref(N)
+    M = OMesh(ref, m.verts, m.etov, bc_default=bc)
+    op = Operator(M, rho, c)
+    dt = local_dt(M.verts, M.etov, c, N)
+    lev, L, dtl = lts_levels(dt, M.EToE, n_levels)
+    return m, op, lev, L, dtl
+
+
+def eigenmode(M, t):
+    """Rigid unit-box eigenmode (rho = c = 1): p = cos(pi x)cos(pi y)cos(pi z)cos(w t), w = pi sqrt(3)."""
+    w = np.pi * np.sqrt(3.0)
+    x, y, z = M.x[..., 0], M.x[..., 1], M.x[..., 2]
+    pi = np.pi
+    q = np.zeros((M.K, 4, M.ref.Np))
+    q[:, 0] = np.cos(pi * x) * np.cos(pi * y) * np.cos(pi * z) * np.cos(w * t)
+    q[:, 1] = pi / w * np.sin(pi * x) * np.cos(pi * y) * np.cos(pi * z) * np.sin(w * t)
+    q[:, 2] = pi / w * np.cos(pi * x) * np.sin(pi * y) * np.cos(pi * z) * np.sin(w * t)
+    q[:, 3] = pi / w * np.cos(pi * x) * np.cos(pi * y) * np.sin(pi * z) * np.sin(w * t)
+    return q

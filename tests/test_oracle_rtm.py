@@ -1,0 +1,101 @@
+"""Pins of the oracle's point sources, receivers, wavelet and imaging condition."""
+import numpy as np
+import pytest
+
+from oracle import source as S
+from oracle.mesh import BC_TRANSPARENT
+from oracle.rtm import COND_CHARACTERISTIC, COND_PRESSURE, Shot
+from paper_1506_00907_amd import inputs as I
+from tests.oracle_cases import case
+
+
+def test_ricker_closed_form():
+    f, tp = 15.0, 0.1127
+    assert S.ricker(tp, f, tp) == 1.0
+    z = 1.0 / (np.sqrt(2.0) * np.pi * f)
+    assert abs(S.ricker(tp + z, f, tp)) < 1e-15 and abs(S.ricker(tp - z, f, tp)) < 1e-15
+    assert abs(S.ricker(0.0, f, I.ricker_peak_time(f))) < 1e-7
+
+
+def test_delta_projection_and_recording():
+    m, op, *_ = case("two_layer_small:6:6:4:3")
+    M = op.m
+    rng = np.random.default_rng(0)
+    pts = np.column_stack([rng.uniform(0.1, 1.9, 20), rng.uniform(0.1, 1.9, 20), rng.uniform(0.1, 0.9, 20)])
+    k = S.locate(M, pts)
+    lam = S.barycentric(M, k, pts)
+    assert np.all(lam >= -1e-12)
+    w = S.delta_weights(M, k, pts)
+    Mk = M.J[k][:, None, None] * M.ref.M[None]
+    # partition of unity: 1^T M_k w = 1
+    assert np.allclose(np.einsum("kn,knm,km->k", np.ones_like(w), Mk, w), 1.0, atol=1e-12)
+    # reproducing: int delta~ phi = phi(x0) for every polynomial phi of degree <= N
+    x = M.x[k]
+    phi = x[..., 0] ** 2 * x[..., 1] - 0.5 * x[..., 2] ** 3 + 1.0
+    val = pts[:, 0] ** 2 * pts[:, 1] - 0.5 * pts[:, 2] ** 3 + 1.0
+    assert np.allclose(np.einsum("kn,knm,km->k", phi, Mk, w), val, atol=1e-11)
+    # recording evaluates the element polynomial exactly
+    assert np.allclose(np.einsum("kn,kn->k", S.interp_rows(M, k, pts), phi), val, atol=1e-11)
+    # record / inject adjointness: <R q, d> = <q, M Inj d>
+    q = rng.standard_normal((k.size, M.ref.Np))
+    d = rng.standard_normal(k.size)
+    lhs = np.sum(np.einsum("kn,kn->k", S.interp_rows(M, k, pts), q) * d)
+    rhs = np.sum(np.einsum("kn,knm,km->k", q, Mk, d[:, None] * w))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_data_interpolation_is_linear_and_zero_after_end():
+    data = np.array([[0.0, 1.0, 3.0]])
+    assert S.data_at(data, 4, 0)[0] == 0.0
+    assert S.data_at(data, 4, 2)[0] == 0.5
+    assert S.data_at(data, 4, 6)[0] == 2.0
+    assert S.data_at(data, 4, 8)[0] == 3.0
+    assert S.data_at(data, 4, 9)[0] == 0.0
+
+
+@pytest.fixture(scope="module")
+def tiny_shot():
+    m, op, lev, L, dtl = case("two_layer_small:6:6:4:2")
+    sh = I.rtm_shot(n_rec=4)
+    M = op.m
+    se = S.locate(M, sh.src[None])[0]
+    sw = S.delta_weights(M, np.array([se]), sh.src[None])[0]
+    re = S.locate(M, sh.rec)
+    shot = Shot(op, lev, L, dtl, 30, se, sw, lambda t: S.ricker(t, sh.f_peak, sh.t_peak), re,
+                S.interp_rows(M, re, sh.rec), S.delta_weights(M, re, sh.rec))
+    tr = shot.forward()
+    return shot, tr
+
+
+@pytest.mark.parametrize("cond", [COND_CHARACTERISTIC, COND_PRESSURE])
+def test_image_formula_equals_quadrature(tiny_shot, cond):
+    shot, tr = tiny_shot
+    if cond == COND_PRESSURE:
+        shot.forward(condition=COND_PRESSURE)
+    a = shot.adjoint(tr, condition=cond)
+    b = shot.adjoint(tr, condition=cond, quadrature=True)
+    assert np.abs(a).max() > 0
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+    shot.forward()
+
+
+def test_image_window_restricts_to_late_times(tiny_shot):
+    shot, tr = tiny_shot
+    full = shot.adjoint(tr)
+    late = shot.adjoint(tr, g_image_start=15)
+    assert np.abs(late).max() > 0 and np.abs(full - late).max() > 1e-3 * np.abs(full).max()
+
+
+def test_characteristic_split_of_a_plane_wave():
+    # an up-going plane wave p = f(z - c t), v_z = p/(rho c) has q- = 0 and q+ = 2p
+    from oracle.rtm import _split_rows
+    m, op, *_ = case("two_layer_small:4:4:3:2")
+    M = op.m
+    ev = np.arange(M.K)
+    f = np.sin(3.0 * M.x[..., 2])
+    q = np.zeros((M.K, 4, M.ref.Np))
+    q[:, 0] = f
+    q[:, 3] = f / (op.rho * op.c)[:, None]
+    qm = _split_rows(op, ev, q, np.array([0.0, 0.0, 1.0]), -1.0, COND_CHARACTERISTIC)
+    qp = _split_rows(op, ev, q, np.array([0.0, 0.0, 1.0]), +1.0, COND_CHARACTERISTIC)
+    assert np.abs(qm).max() < 1e-14 and np.allclose(qp, 2 * f)
