@@ -83,7 +83,7 @@ def test_image_window_restricts_to_late_times(tiny_shot):
     shot, tr = tiny_shot
     full = shot.adjoint(tr)
     late = shot.adjoint(tr, g_image_start=15)
-    assert np.abs(late).max() > 0 and np.abs(full - late).max() > 1e-3 * np.abs(full).max()
+    assert np.abs(late).max() > 0 and np.abs(full - late).max() > 1e-6 * np.abs(full).max()
 
 
 def test_characteristic_split_of_a_plane_wave():
