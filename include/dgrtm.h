@@ -1,0 +1,205 @@
+/*
+ * dgrtm: nodal discontinuous-Galerkin reverse-time migration on one AMD Instinct MI355X (gfx950).
+ *
+ * The C ABI of libdgrtm.so.  It computes what Modave, St-Cyr, Mulder and Warburton,
+ * "Nodal Discontinuous Galerkin Simulations for Reverse-Time Migration on GPU Clusters"
+ * (arXiv 1506.00907), define:
+ *   - the first-order acoustic pressure-velocity system with piecewise-constant rho and c,
+ *     a point source f(t) delta(x - x0) in the pressure equation, and free-surface,
+ *     transparent (p - rho c n.v = 0) or rigid boundaries (model section, eqs. waveSyst1/2, ABC);
+ *   - its nodal DG discretisation on tetrahedra with penalty fluxes (nodal-DG section,
+ *     eqs. weakFormP/V, dgLocalSchemeP/U, the appendix);
+ *   - multi-rate Adams-Bashforth time stepping on levels Delta t_l = 2^(L-l) Delta t_local
+ *     (time-stepping section, eqs. updateAB, updateABcoarse; Alg. 1);
+ *   - the RTM procedure: forward source wavefield, backward receiver wavefield with the
+ *     recorded data re-injected, and the imaging condition accumulated step by step from the
+ *     AB3 dense-output polynomials of both fields (model section, eqs. imageP and imageQ;
+ *     imaging section, eq. updateABcorr).
+ *
+ * Conventions (every entry point):
+ *   - Return value: DGRTM_OK (0) or a negative error code; dgrtm_last_error() returns a
+ *     thread-local message describing the last failure.
+ *   - Host arrays passed in are copied during the call; the caller keeps ownership.
+ *   - Device memory is never allocated by the library: every handle that owns device state
+ *     works inside a caller-provided device workspace of the size the matching *_bytes query
+ *     returns.  The caller keeps that workspace alive until the handle is destroyed.
+ *   - Work is enqueued asynchronously on the HIP stream given at dgrtm_mesh_bind; calls that
+ *     return host values synchronise that stream.  Handles are not thread-safe.
+ *   - Element numbering in every array is the caller's ("user order"); the library reorders
+ *     elements internally (finest time level first).
+ *   - Units are any consistent set (the tests use km, s, km/s, g/cm^3).
+ */
+#ifndef DGRTM_H
+#define DGRTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dgrtm_status;
+#define DGRTM_OK 0
+#define DGRTM_ERR_ARG (-1)       /* invalid argument or call order */
+#define DGRTM_ERR_WORKSPACE (-2) /* workspace too small (query the *_bytes call) */
+#define DGRTM_ERR_MESH (-3)      /* invalid mesh: degenerate element, non-manifold face, bad index */
+#define DGRTM_ERR_OUTSIDE (-4)   /* a source or receiver point lies outside the mesh */
+#define DGRTM_ERR_HIP (-5)       /* a HIP runtime call failed */
+
+/* boundary types of a boundary face (model section: free surface p = 0, transparent
+ * p - rho c n.v = 0; rigid wall n.v = 0) */
+#define DGRTM_BC_RIGID 1
+#define DGRTM_BC_TRANSPARENT 2
+#define DGRTM_BC_FREE 3
+
+/* imaging conditions: classical p_S p_R (eq. imageP) or characteristic q-_S q+_R with
+ * q+- = p +- rho c up.v (eqs. imageQ, charact) */
+#define DGRTM_IMAGE_PRESSURE 0
+#define DGRTM_IMAGE_CHARACTERISTIC 1
+
+/* which wavefield of a shot a test hook addresses */
+#define DGRTM_SOURCE_FIELD 0
+#define DGRTM_RECEIVER_FIELD 1
+
+typedef struct dgrtm_mesh_s *dgrtm_mesh;
+typedef struct dgrtm_shot_s *dgrtm_shot;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *dgrtm_last_error(void);
+
+/*
+ * Build the order-N reference element (warp-and-blend nodes, D_r, D_s, D_t, LIFT; nodal-DG
+ * section and appendix), the face connectivity and the geometric factors of a tetrahedral mesh.
+ *   N          polynomial order, 1..6
+ *   vert_xyz   host, n_vert x 3 doubles
+ *   elem_vert  host, n_elem x 4 vertex indices; elements with negative volume are re-oriented
+ *   face_bc    host, n_elem x 4 boundary types (DGRTM_BC_*) read on boundary faces only, or
+ *              NULL to use bc_default everywhere
+ * Host work only.  Errors: DGRTM_ERR_ARG, DGRTM_ERR_MESH.
+ */
+dgrtm_status dgrtm_mesh_create(int N, int64_t n_vert, const double *vert_xyz, int64_t n_elem,
+                               const int64_t *elem_vert, const int8_t *face_bc, int bc_default,
+                               dgrtm_mesh *out);
+
+/*
+ * Set per-element density and velocity and assign multi-rate levels (time-stepping section):
+ * dt_k = cfl * l_k / ((N+1)^2 c_k) with l_k the smallest face-to-opposite-vertex distance
+ * (validation section), dt_local = min_k dt_k, level l_k the coarsest l in 1..n_levels_max
+ * with 2^(L-l) dt_local <= dt_k, levels then raised until face neighbours differ by at most
+ * one, and empty coarse levels removed.  n_levels_max = 1 gives single-rate AB3.
+ *   rho, c        host, n_elem doubles, > 0
+ *   dt_local_out  receives dt_local; n_levels_out receives the number of levels L (NULL ok)
+ * Host work only; must precede dgrtm_mesh_bind.  Errors: DGRTM_ERR_ARG.
+ */
+dgrtm_status dgrtm_set_model(dgrtm_mesh mesh, const double *rho, const double *c, int n_levels_max,
+                             double cfl, double *dt_local_out, int *n_levels_out);
+
+/* Device bytes dgrtm_mesh_bind needs (operators, geometry, connectivity). */
+dgrtm_status dgrtm_mesh_bytes(dgrtm_mesh mesh, size_t *bytes);
+
+/*
+ * Upload the mesh into the device workspace dev_ws (>= dgrtm_mesh_bytes, 256-byte aligned)
+ * and bind the handle to hip_stream (a hipStream_t; NULL = default stream).
+ * Errors: DGRTM_ERR_ARG, DGRTM_ERR_WORKSPACE, DGRTM_ERR_HIP.
+ */
+dgrtm_status dgrtm_mesh_bind(dgrtm_mesh mesh, void *dev_ws, size_t ws_bytes, void *hip_stream);
+
+/*
+ * Export the integer set-up for checking (host arrays, user element order, any may be NULL):
+ *   EToE, EToF  n_elem x 4 neighbour element and face (self on a boundary face)
+ *   vmapP       n_elem x 4 x Nfp global node id k*Np+n of the matching node on the other side
+ *   level       n_elem multi-rate level (1 = coarsest)
+ *   sorted_pos  n_elem position of each element in the device order
+ */
+dgrtm_status dgrtm_export_setup(dgrtm_mesh mesh, int32_t *EToE, int8_t *EToF, int32_t *vmapP,
+                                int8_t *level, int64_t *sorted_pos);
+
+/* Reference operators in FP64 (host, row-major): Dr, Ds, Dt (Np x Np), LIFT (Np x 4 Nfp),
+ * node coordinates rst (Np x 3).  Any pointer may be NULL. */
+dgrtm_status dgrtm_export_operators(dgrtm_mesh mesh, double *Dr, double *Ds, double *Dt, double *LIFT,
+                                    double *rst);
+
+/* Sizes: Np, Nfp, L, number of global steps and local steps per global step are queried per shot. */
+dgrtm_status dgrtm_mesh_info(dgrtm_mesh mesh, int *N, int *Np, int *Nfp, int64_t *n_elem, int *n_levels,
+                             double *dt_local);
+
+void dgrtm_mesh_destroy(dgrtm_mesh mesh);
+
+/* One RTM shot (versioned plain struct: set struct_size = sizeof(dgrtm_shot_args)). */
+typedef struct dgrtm_shot_args {
+  int32_t struct_size;
+  int32_t has_source;      /* 0: no source term (test runs) */
+  double src_xyz[3];
+  double f_peak, t_peak, amp; /* Ricker source f(t) = amp (1 - 2 a) exp(-a), a = (pi f_peak (t - t_peak))^2 */
+  const float *wavelet;    /* host, optional: f sampled at every local step j*dt_local, j = 0..n_steps;
+                              overrides the Ricker when not NULL (length from dgrtm_shot_steps) */
+  int64_t n_rec;           /* receivers: pressure recorded at every global step, re-injected backward */
+  const double *rec_xyz;   /* host, n_rec x 3 */
+  double t_final;          /* rounded up to a whole number of global steps */
+  int64_t ckpt_interval;   /* global steps between source checkpoints; 0 = chosen to minimise memory */
+} dgrtm_shot_args;
+
+/* Number of global steps of a shot and local steps per global step. */
+dgrtm_status dgrtm_shot_steps(dgrtm_mesh mesh, const dgrtm_shot_args *args, int64_t *n_global,
+                              int32_t *n_local);
+
+/* Device bytes of a shot: both wavefields, FP64 image, checkpoints, segment buffer, traces. */
+dgrtm_status dgrtm_shot_bytes(dgrtm_mesh mesh, const dgrtm_shot_args *args, size_t *bytes);
+
+/*
+ * Create a shot inside dev_ws (>= dgrtm_shot_bytes): locates the source and receivers (the
+ * lowest-numbered element whose barycentric coordinates are all >= -1e-12) and projects the
+ * point delta on the element's polynomial space, w = M_k^{-1} l(x0) (eq. sourceTerm).
+ * Errors: DGRTM_ERR_ARG, DGRTM_ERR_WORKSPACE, DGRTM_ERR_OUTSIDE, DGRTM_ERR_HIP.
+ */
+dgrtm_status dgrtm_shot_create(dgrtm_mesh mesh, const dgrtm_shot_args *args, void *dev_ws, size_t ws_bytes,
+                               dgrtm_shot *out);
+
+/*
+ * Forward source run from rest over [0, t_final] with multi-rate AB3 (Alg. 1), saving the AB3
+ * state every ckpt_interval global steps in the workspace.  traces_out (device, may be NULL)
+ * receives the recorded pressure, n_rec x (n_global + 1) floats, sample g at t = g dt_global.
+ */
+dgrtm_status dgrtm_forward(dgrtm_shot shot, float *traces_out);
+
+/*
+ * Backward receiver run with the data re-injected and the image accumulated (FP64).
+ *   data        device, n_rec x (n_global + 1) floats (linear in time between samples, 0 after t_final)
+ *   condition   DGRTM_IMAGE_PRESSURE or DGRTM_IMAGE_CHARACTERISTIC
+ *   up          host, 3 doubles: the "up" unit vector of the characteristic split
+ *   g_image_start  image only over [g_image_start dt_global, t_final]; the backward run stops there
+ * The source wavefield is recomputed segment by segment from the checkpoints.  Requires a
+ * completed dgrtm_forward.  The image is reset at the start of the call.
+ */
+dgrtm_status dgrtm_adjoint(dgrtm_shot shot, const float *data, int condition, const double *up,
+                           int64_t g_image_start);
+
+/* Copy (accumulate = 0) or add (accumulate = 1) the FP64 image into image_out (device, n_elem x Np). */
+dgrtm_status dgrtm_image(dgrtm_shot shot, double *image_out, int accumulate);
+
+/* Sum over all samples of (a - b)^2 in FP64 (device float arrays of n values); result on host. */
+dgrtm_status dgrtm_residual(dgrtm_shot shot, const float *a, const float *b, int64_t n, double *out);
+
+/* ---- test hooks (device arrays in user order: n_elem x 4 fields (p, vx, vy, vz) x Np) ---- */
+
+/* Right-hand side of the semi-discrete system for the given state (no source), forward time
+ * (reversed = 0) or reversed time -L(q; -tau) (reversed = 1).  Uses the shot's source-field buffers. */
+dgrtm_status dgrtm_apply_rhs(dgrtm_shot shot, const float *q, float *rhs, int reversed);
+
+/* Set a wavefield's state at time 0 and its AB3 history r(-dt), r(-2 dt) (either may be NULL = 0). */
+dgrtm_status dgrtm_set_state(dgrtm_shot shot, int which, const float *q, const float *hist1, const float *hist2);
+
+/* Read a wavefield's current state. */
+dgrtm_status dgrtm_get_state(dgrtm_shot shot, int which, float *q);
+
+/* Advance a wavefield by n_global global steps (forward; reversed = 1 uses -L(q; -tau)),
+ * with the shot's source when with_source != 0 and the wavefield is the source field. */
+dgrtm_status dgrtm_run(dgrtm_shot shot, int which, int64_t n_global, int reversed, int with_source);
+
+void dgrtm_shot_destroy(dgrtm_shot shot);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGRTM_H */

@@ -1,0 +1,791 @@
+// C ABI of libdgrtm: host driver of the multi-rate DG solver and the RTM procedure.
+#include "../../include/dgrtm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "setup.hpp"
+
+using namespace dgrtm;
+
+namespace {
+thread_local std::string g_err;
+
+dgrtm_status fail(dgrtm_status code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) return fail(DGRTM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// bump allocator inside a caller-provided device workspace (256-byte aligned slices)
+struct Bump {
+  char *base = nullptr;
+  size_t used = 0, cap = 0;
+  template <class T>
+  T *take(size_t n) {
+    used = (used + 255) / 256 * 256;
+    T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+    used += n * sizeof(T);
+    return p;
+  }
+};
+}  // namespace
+
+struct dgrtm_mesh_s {
+  RefOps ref;
+  HostMesh hm;
+  bool bound = false;
+  hipStream_t stream = nullptr;
+  // device
+  float *geo = nullptr;
+  int *nbr = nullptr, *ncode = nullptr, *eflag = nullptr;
+  float *ops = nullptr;
+  int8_t *nbr_index = nullptr;
+  int64_t *s2u = nullptr;
+  std::vector<int> h_eflag;  // base flags (valid, has finer neighbour)
+  int64_t n_ops = 0;
+};
+
+struct PointSet {
+  int64_t n = 0;
+  int64_t *pos = nullptr;      // sorted positions (recording)
+  float *interp = nullptr;     // n x Np Lagrange values (recording)
+  float *w = nullptr;          // n x Np delta weights (injection)
+  int *start = nullptr, *count = nullptr, *point = nullptr;  // CSR over sorted positions
+  int *eflag = nullptr;        // mesh flags | 4 where points inject
+};
+
+struct Field {
+  float *q = nullptr, *ring = nullptr, *tr = nullptr;
+  int64_t tau = 0;
+};
+
+struct dgrtm_shot_s {
+  dgrtm_mesh mesh = nullptr;
+  dgrtm_shot_args args{};
+  int64_t n_global = 0;
+  int n_local = 1;
+  int64_t C = 1, n_ckpt = 0;
+  Field S, R;
+  double *img = nullptr;
+  float *ckpt = nullptr;
+  float *seg_q = nullptr, *seg_r = nullptr;
+  int64_t seg_q_off[kMaxLevels] = {0}, seg_r_off[kMaxLevels] = {0};
+  PointSet src, rec;
+  float *wavelet = nullptr;
+  float *traces = nullptr;     // n_rec x (n_global + 1)
+  double *red = nullptr;       // FP64 reduction scratch
+  bool forward_done = false;
+};
+
+static int64_t level_end_h(const HostMesh &m, int l) { return l == 1 ? m.lev_begin[m.L] : m.lev_begin[l - 2]; }
+static int64_t level_size_h(const HostMesh &m, int l) { return level_end_h(m, l) - m.lev_begin[l - 1]; }
+
+extern "C" const char *dgrtm_last_error(void) { return g_err.c_str(); }
+
+extern "C" dgrtm_status dgrtm_mesh_create(int N, int64_t n_vert, const double *vert_xyz, int64_t n_elem,
+                                          const int64_t *elem_vert, const int8_t *face_bc, int bc_default,
+                                          dgrtm_mesh *out) {
+  if (!out || N < 1 || N > 6 || n_vert < 4 || n_elem < 1 || !vert_xyz || !elem_vert)
+    return fail(DGRTM_ERR_ARG, "dgrtm_mesh_create: bad argument (N must be 1..6)");
+  if (n_elem > (int64_t)1 << 30) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_create: too many elements");
+  if (!face_bc && (bc_default < 1 || bc_default > 3)) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_create: bad bc_default");
+  auto *m = new dgrtm_mesh_s();
+  build_ref(N, m->ref);
+  std::string err = mesh_build(m->hm, N, n_vert, vert_xyz, n_elem, elem_vert, face_bc, bc_default, m->ref);
+  if (!err.empty()) {
+    delete m;
+    return fail(DGRTM_ERR_MESH, "dgrtm_mesh_create: " + err);
+  }
+  *out = m;
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_set_model(dgrtm_mesh m, const double *rho, const double *c, int n_levels_max,
+                                        double cfl, double *dt_local_out, int *n_levels_out) {
+  if (!m || !rho || !c || !(cfl > 0)) return fail(DGRTM_ERR_ARG, "dgrtm_set_model: bad argument");
+  if (m->bound) return fail(DGRTM_ERR_ARG, "dgrtm_set_model: mesh already bound");
+  std::string err = mesh_set_model(m->hm, rho, c, n_levels_max, cfl);
+  if (!err.empty()) return fail(DGRTM_ERR_ARG, "dgrtm_set_model: " + err);
+  if (dt_local_out) *dt_local_out = m->hm.dt_local;
+  if (n_levels_out) *n_levels_out = m->hm.L;
+  return DGRTM_OK;
+}
+
+static size_t mesh_layout(dgrtm_mesh m, Bump &b) {
+  const HostMesh &h = m->hm;
+  const int64_t K = h.Ktot;
+  const int64_t n_ops = op_fragment_floats(m->ref.N);
+  float *geo = b.take<float>((size_t)kGeo * K);
+  int *nbr = b.take<int>((size_t)4 * K);
+  int *ncode = b.take<int>((size_t)4 * K);
+  int *eflag = b.take<int>((size_t)K);
+  float *ops = b.take<float>((size_t)n_ops);
+  int8_t *nidx = b.take<int8_t>((size_t)4 * 4 * 6 * m->ref.Nfp);
+  int64_t *s2u = b.take<int64_t>((size_t)K);
+  if (b.base) {  // a sizing pass (no base) leaves the handle untouched
+    m->geo = geo;
+    m->nbr = nbr;
+    m->ncode = ncode;
+    m->eflag = eflag;
+    m->n_ops = n_ops;
+    m->ops = ops;
+    m->nbr_index = nidx;
+    m->s2u = s2u;
+  }
+  return b.used;
+}
+
+extern "C" dgrtm_status dgrtm_mesh_bytes(dgrtm_mesh m, size_t *bytes) {
+  if (!m || !bytes) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_bytes: bad argument");
+  if (!m->hm.has_model) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_bytes: call dgrtm_set_model first");
+  Bump b;
+  *bytes = mesh_layout(m, b) + 256;
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_bytes, void *hip_stream) {
+  if (!m || !dev_ws) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_bind: bad argument");
+  if (!m->hm.has_model) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_bind: call dgrtm_set_model first");
+  if (((uintptr_t)dev_ws) % 256) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_bind: workspace must be 256-byte aligned");
+  Bump probe;
+  size_t need = mesh_layout(m, probe);
+  if (ws_bytes < need) return fail(DGRTM_ERR_WORKSPACE, "dgrtm_mesh_bind: workspace too small");
+  Bump b;
+  b.base = (char *)dev_ws;
+  mesh_layout(m, b);
+  m->stream = (hipStream_t)hip_stream;
+  const HostMesh &h = m->hm;
+  const RefOps &R = m->ref;
+  const int64_t K = h.Ktot;
+  // geometry and material in device order; padding slots get an identity metric and unit material
+  std::vector<float> geo((size_t)kGeo * K, 0.0f);
+  std::vector<int> nbr((size_t)4 * K, -2), ncode((size_t)4 * K, 0);
+  m->h_eflag.assign(K, 0);
+  for (int64_t s = 0; s < K; ++s) {
+    int64_t u = h.sorted_to_user[s];
+    if (u < 0) {
+      geo[0 * K + s] = geo[4 * K + s] = geo[8 * K + s] = 1.0f;
+      geo[9 * K + s] = geo[10 * K + s] = geo[11 * K + s] = 1.0f;
+      continue;
+    }
+    for (int i = 0; i < 9; ++i) geo[i * K + s] = (float)h.geo[9 * u + i];
+    const double Zm = h.rho[u] * h.c[u];
+    geo[9 * K + s] = (float)(h.rho[u] * h.c[u] * h.c[u]);
+    geo[10 * K + s] = (float)(1.0 / h.rho[u]);
+    geo[11 * K + s] = (float)Zm;
+    int flag = 1;
+    for (int f = 0; f < 4; ++f) {
+      const int64_t u2 = h.EToE[4 * u + f];
+      const int b_ = h.bc[4 * u + f];
+      double taup, tauv;
+      if (b_ != 0) {
+        taup = 1.0 / Zm;
+        tauv = Zm;
+        nbr[f * K + s] = -b_;
+      } else {
+        const double Zp = h.rho[u2] * h.c[u2];
+        taup = 2.0 / (Zm + Zp);
+        tauv = 0.5 * (Zm + Zp);
+        nbr[f * K + s] = (int)h.user_to_sorted[u2];
+        ncode[f * K + s] = h.EToF[4 * u + f] | (h.face_perm[4 * u + f] << 2) | (h.level[u2] << 5);
+        if (h.level[u2] > h.level[u]) flag |= 2;
+      }
+      geo[(12 + f) * K + s] = (float)taup;
+      geo[(16 + f) * K + s] = (float)tauv;
+    }
+    m->h_eflag[s] = flag;
+  }
+  const int Np = R.Np, F = 4 * R.Nfp;
+  std::vector<float> Dr(Np * Np), Ds(Np * Np), Dt(Np * Np), L(Np * F);
+  for (int i = 0; i < Np * Np; ++i) {
+    Dr[i] = (float)R.Dr[i];
+    Ds[i] = (float)R.Ds[i];
+    Dt[i] = (float)R.Dt[i];
+  }
+  for (int i = 0; i < Np * F; ++i) L[i] = (float)R.LIFT[i];
+  std::vector<float> frag(m->n_ops);
+  build_op_fragments(R.N, Dr.data(), Ds.data(), Dt.data(), L.data(), frag.data());
+  std::vector<int8_t> nidx(R.nbr_index.size());
+  for (size_t i = 0; i < nidx.size(); ++i) nidx[i] = (int8_t)R.nbr_index[i];
+  hipStream_t st = m->stream;
+  HIPCHK(hipMemcpyAsync(m->geo, geo.data(), geo.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(m->nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(m->ncode, ncode.data(), ncode.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(m->eflag, m->h_eflag.data(), K * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(m->ops, frag.data(), frag.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(m->nbr_index, nidx.data(), nidx.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(m->s2u, h.sorted_to_user.data(), K * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  m->bound = true;
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_export_setup(dgrtm_mesh m, int32_t *EToE, int8_t *EToF, int32_t *vmapP, int8_t *level,
+                                           int64_t *sorted_pos) {
+  if (!m) return fail(DGRTM_ERR_ARG, "dgrtm_export_setup: bad argument");
+  const HostMesh &h = m->hm;
+  if (EToE) std::copy(h.EToE.begin(), h.EToE.end(), EToE);
+  if (EToF) std::copy(h.EToF.begin(), h.EToF.end(), EToF);
+  if (vmapP) mesh_vmapP(h, m->ref, vmapP);
+  if (level || sorted_pos) {
+    if (!h.has_model) return fail(DGRTM_ERR_ARG, "dgrtm_export_setup: levels need dgrtm_set_model");
+    if (level) std::copy(h.level.begin(), h.level.end(), level);
+    if (sorted_pos) std::copy(h.user_to_sorted.begin(), h.user_to_sorted.end(), sorted_pos);
+  }
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_export_operators(dgrtm_mesh m, double *Dr, double *Ds, double *Dt, double *LIFT,
+                                               double *rst) {
+  if (!m) return fail(DGRTM_ERR_ARG, "dgrtm_export_operators: bad argument");
+  const RefOps &R = m->ref;
+  if (Dr) std::copy(R.Dr.begin(), R.Dr.end(), Dr);
+  if (Ds) std::copy(R.Ds.begin(), R.Ds.end(), Ds);
+  if (Dt) std::copy(R.Dt.begin(), R.Dt.end(), Dt);
+  if (LIFT) std::copy(R.LIFT.begin(), R.LIFT.end(), LIFT);
+  if (rst)
+    for (int n = 0; n < R.Np; ++n) {
+      rst[3 * n] = R.r[n];
+      rst[3 * n + 1] = R.s[n];
+      rst[3 * n + 2] = R.t[n];
+    }
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_mesh_info(dgrtm_mesh m, int *N, int *Np, int *Nfp, int64_t *n_elem, int *n_levels,
+                                        double *dt_local) {
+  if (!m) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_info: bad argument");
+  if (N) *N = m->ref.N;
+  if (Np) *Np = m->ref.Np;
+  if (Nfp) *Nfp = m->ref.Nfp;
+  if (n_elem) *n_elem = m->hm.K;
+  if (n_levels) *n_levels = m->hm.L;
+  if (dt_local) *dt_local = m->hm.dt_local;
+  return DGRTM_OK;
+}
+
+extern "C" void dgrtm_mesh_destroy(dgrtm_mesh m) { delete m; }
+
+// ------------------------------------------------------------------------------------------------
+// shots
+// ------------------------------------------------------------------------------------------------
+static dgrtm_status check_args(dgrtm_mesh m, const dgrtm_shot_args *a) {
+  if (!m || !a) return fail(DGRTM_ERR_ARG, "bad argument");
+  if (a->struct_size != (int32_t)sizeof(dgrtm_shot_args)) return fail(DGRTM_ERR_ARG, "dgrtm_shot_args: struct_size mismatch");
+  if (!m->hm.has_model) return fail(DGRTM_ERR_ARG, "call dgrtm_set_model first");
+  if (!(a->t_final > 0)) return fail(DGRTM_ERR_ARG, "t_final must be positive");
+  if (a->n_rec < 0 || (a->n_rec > 0 && !a->rec_xyz)) return fail(DGRTM_ERR_ARG, "bad receivers");
+  if (a->ckpt_interval < 0) return fail(DGRTM_ERR_ARG, "bad ckpt_interval");
+  return DGRTM_OK;
+}
+
+static void shot_steps(dgrtm_mesh m, const dgrtm_shot_args *a, int64_t &ng, int &nl) {
+  nl = 1 << (m->hm.L - 1);
+  const double dtg = m->hm.dt_local * nl;
+  ng = std::max<int64_t>(1, (int64_t)std::ceil(a->t_final / dtg - 1e-9));
+}
+
+extern "C" dgrtm_status dgrtm_shot_steps(dgrtm_mesh m, const dgrtm_shot_args *a, int64_t *n_global, int32_t *n_local) {
+  dgrtm_status s = check_args(m, a);
+  if (s) return s;
+  int64_t ng;
+  int nl;
+  shot_steps(m, a, ng, nl);
+  if (n_global) *n_global = ng;
+  if (n_local) *n_local = nl;
+  return DGRTM_OK;
+}
+
+static int64_t choose_interval(dgrtm_mesh m, const dgrtm_shot_args *a, int64_t ng) {
+  if (a->ckpt_interval > 0) return std::min(a->ckpt_interval, ng);
+  const HostMesh &h = m->hm;
+  const int Np = m->ref.Np;
+  double ck = 12.0 * Np * h.Ktot;
+  double seg = 0;
+  for (int l = 1; l <= h.L; ++l) seg += 2.0 * Np * (double)level_size_h(h, l) * (1 << (l - 1));
+  int64_t C = (int64_t)std::llround(std::sqrt((double)ng * ck / std::max(seg, 1.0)));
+  return std::min<int64_t>(std::max<int64_t>(C, 1), ng);
+}
+
+static size_t shot_layout(dgrtm_shot sh, Bump &b) {
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  const int Np = m->ref.Np, F = 4 * m->ref.Nfp;
+  const int64_t K = h.Ktot;
+  for (Field *f : {&sh->S, &sh->R}) {
+    f->q = b.take<float>((size_t)4 * Np * K);
+    f->ring = b.take<float>((size_t)12 * Np * K);
+    f->tr = b.take<float>((size_t)6 * F * K);
+  }
+  sh->img = b.take<double>((size_t)Np * K);
+  sh->ckpt = b.take<float>((size_t)sh->n_ckpt * 12 * Np * K);
+  int64_t oq = 0, orr = 0;
+  for (int l = 1; l <= h.L; ++l) {
+    const int64_t P = level_size_h(h, l), nst = sh->C * ((int64_t)1 << (l - 1));
+    sh->seg_q_off[l - 1] = oq;
+    sh->seg_r_off[l - 1] = orr;
+    oq += nst * Np * P;
+    orr += (nst + 2) * Np * P;
+  }
+  sh->seg_q = b.take<float>((size_t)oq);
+  sh->seg_r = b.take<float>((size_t)orr);
+  for (PointSet *p : {&sh->src, &sh->rec}) {
+    p->pos = b.take<int64_t>((size_t)std::max<int64_t>(p->n, 1));
+    p->interp = b.take<float>((size_t)std::max<int64_t>(p->n, 1) * Np);
+    p->w = b.take<float>((size_t)std::max<int64_t>(p->n, 1) * Np);
+    p->start = b.take<int>((size_t)K);
+    p->count = b.take<int>((size_t)K);
+    p->point = b.take<int>((size_t)std::max<int64_t>(p->n, 1));
+    p->eflag = b.take<int>((size_t)K);
+  }
+  sh->wavelet = b.take<float>((size_t)sh->n_global * sh->n_local + 1);
+  sh->traces = b.take<float>((size_t)std::max<int64_t>(sh->rec.n, 1) * (sh->n_global + 1));
+  sh->red = b.take<double>(8);
+  return b.used;
+}
+
+static dgrtm_shot new_shot(dgrtm_mesh m, const dgrtm_shot_args *a) {
+  auto *sh = new dgrtm_shot_s();
+  sh->mesh = m;
+  sh->args = *a;
+  shot_steps(m, a, sh->n_global, sh->n_local);
+  sh->C = choose_interval(m, a, sh->n_global);
+  sh->n_ckpt = (sh->n_global + sh->C - 1) / sh->C;
+  sh->src.n = a->has_source ? 1 : 0;
+  sh->rec.n = a->n_rec;
+  return sh;
+}
+
+extern "C" dgrtm_status dgrtm_shot_bytes(dgrtm_mesh m, const dgrtm_shot_args *a, size_t *bytes) {
+  dgrtm_status s = check_args(m, a);
+  if (s) return s;
+  if (!bytes) return fail(DGRTM_ERR_ARG, "dgrtm_shot_bytes: bad argument");
+  dgrtm_shot sh = new_shot(m, a);
+  Bump b;
+  *bytes = shot_layout(sh, b) + 256;
+  delete sh;
+  return DGRTM_OK;
+}
+
+// locate points, build per-point interpolation rows / delta weights and the CSR lists
+static dgrtm_status upload_points(dgrtm_shot sh, PointSet &p, const double *xyz) {
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  const RefOps &R = m->ref;
+  const int Np = R.Np;
+  const int64_t K = h.Ktot;
+  std::vector<int64_t> elem(p.n);
+  std::vector<double> rst(3 * p.n);
+  if (p.n) locate_points(h, p.n, xyz, elem.data(), rst.data());
+  std::vector<double> Vt(Np * Np);  // V^T for solving l = V^{-T} psi
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j) Vt[i * Np + j] = R.V[j * Np + i];
+  std::vector<double> Vti = Vt;
+  invert(Np, Vti);
+  std::vector<float> interp(std::max<int64_t>(p.n, 1) * Np), w(std::max<int64_t>(p.n, 1) * Np);
+  std::vector<int64_t> pos(std::max<int64_t>(p.n, 1), 0);
+  std::vector<double> psi(Np);
+  for (int64_t i = 0; i < p.n; ++i) {
+    if (elem[i] < 0) return fail(DGRTM_ERR_OUTSIDE, "point " + std::to_string(i) + " lies outside the mesh");
+    basis_at(R, rst[3 * i], rst[3 * i + 1], rst[3 * i + 2], psi.data());
+    pos[i] = h.user_to_sorted[elem[i]];
+    const double J = h.J[elem[i]];
+    for (int n = 0; n < Np; ++n) {
+      double l = 0.0, wv = 0.0;
+      for (int j = 0; j < Np; ++j) {
+        l += Vti[n * Np + j] * psi[j];
+        wv += R.V[n * Np + j] * psi[j];
+      }
+      interp[i * Np + n] = (float)l;
+      w[i * Np + n] = (float)(wv / J);  // M_k^{-1} l(x0) = (1/J) V psi(r0)
+    }
+  }
+  // CSR: points grouped by sorted position
+  std::vector<int> start(K, 0), count(K, 0), point(std::max<int64_t>(p.n, 1), 0);
+  for (int64_t i = 0; i < p.n; ++i) count[pos[i]]++;
+  int acc = 0;
+  for (int64_t s = 0; s < K; ++s) {
+    start[s] = acc;
+    acc += count[s];
+  }
+  std::vector<int> fill(start);
+  for (int64_t i = 0; i < p.n; ++i) point[fill[pos[i]]++] = (int)i;
+  std::vector<int> ef(m->h_eflag);
+  for (int64_t s = 0; s < K; ++s)
+    if (count[s]) ef[s] |= 4;
+  hipStream_t st = m->stream;
+  HIPCHK(hipMemcpyAsync(p.pos, pos.data(), pos.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p.interp, interp.data(), interp.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p.w, w.data(), w.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p.start, start.data(), K * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p.count, count.data(), K * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p.point, point.data(), point.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p.eflag, ef.data(), K * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_shot_create(dgrtm_mesh m, const dgrtm_shot_args *a, void *dev_ws, size_t ws_bytes,
+                                          dgrtm_shot *out) {
+  dgrtm_status s = check_args(m, a);
+  if (s) return s;
+  if (!out || !dev_ws) return fail(DGRTM_ERR_ARG, "dgrtm_shot_create: bad argument");
+  if (!m->bound) return fail(DGRTM_ERR_ARG, "dgrtm_shot_create: mesh not bound");
+  if (((uintptr_t)dev_ws) % 256) return fail(DGRTM_ERR_ARG, "dgrtm_shot_create: workspace must be 256-byte aligned");
+  dgrtm_shot sh = new_shot(m, a);
+  Bump probe;
+  if (ws_bytes < shot_layout(sh, probe)) {
+    delete sh;
+    return fail(DGRTM_ERR_WORKSPACE, "dgrtm_shot_create: workspace too small");
+  }
+  Bump b;
+  b.base = (char *)dev_ws;
+  shot_layout(sh, b);
+  if ((s = upload_points(sh, sh->src, a->src_xyz)) || (s = upload_points(sh, sh->rec, a->rec_xyz))) {
+    delete sh;
+    return s;
+  }
+  // source signal at every local step (FP64 on the host, stored FP32)
+  const int64_t nst = sh->n_global * sh->n_local + 1;
+  std::vector<float> wav(nst, 0.0f);
+  for (int64_t j = 0; j < nst; ++j) {
+    if (a->wavelet) wav[j] = a->wavelet[j];
+    else {
+      const double t = j * m->hm.dt_local;
+      const double x = M_PI * a->f_peak * (t - a->t_peak);
+      wav[j] = (float)(a->amp * (1.0 - 2.0 * x * x) * std::exp(-x * x));
+    }
+  }
+  hipStream_t st = m->stream;
+  hipError_t e = hipMemcpyAsync(sh->wavelet, wav.data(), nst * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete sh;
+    return fail(DGRTM_ERR_HIP, std::string("dgrtm_shot_create: ") + hipGetErrorString(e));
+  }
+  *out = sh;
+  return DGRTM_OK;
+}
+
+extern "C" void dgrtm_shot_destroy(dgrtm_shot sh) { delete sh; }
+
+// ------------------------------------------------------------------------------------------------
+// time stepping
+// ------------------------------------------------------------------------------------------------
+static void fill_level_begin(const HostMesh &h, int64_t *lb) {
+  for (int i = 0; i <= kMaxLevels; ++i) lb[i] = 0;
+  for (int l = 0; l <= h.L; ++l) lb[l] = h.lev_begin[l];
+}
+
+static StepArgs base_args(dgrtm_shot sh, Field &f, bool reversed) {
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.geo = m->geo;
+  a.nbr = m->nbr;
+  a.ncode = m->ncode;
+  a.eflag = m->eflag;
+  a.ops = m->ops;
+  a.nbr_index = m->nbr_index;
+  a.Ktot = h.Ktot;
+  a.L = h.L;
+  fill_level_begin(h, a.lev_begin);
+  a.q = f.q;
+  a.ring = f.ring;
+  a.tr = f.tr;
+  a.dt_local = h.dt_local;
+  a.tau_sign = reversed ? -1.0f : 1.0f;
+  a.out_sign = reversed ? -1.0f : 1.0f;
+  a.n_local = sh->n_local;
+  a.up[2] = 1.0f;
+  return a;
+}
+
+// end of the active prefix at local step tau: levels whose step starts at tau
+static int64_t active_end(const HostMesh &h, int64_t tau) {
+  for (int l = 1; l <= h.L; ++l)
+    if ((tau & (((int64_t)1 << (h.L - l)) - 1)) == 0) return level_end_h(h, l);
+  return level_end_h(h, h.L);
+}
+
+static dgrtm_status trace_init(dgrtm_shot sh, Field &f) {
+  dgrtm_mesh m = sh->mesh;
+  TraceInitArgs t;
+  std::memset(&t, 0, sizeof(t));
+  t.q = f.q;
+  t.tr = f.tr;
+  t.geo = m->geo;
+  t.eflag = m->eflag;
+  t.Ktot = m->hm.Ktot;
+  t.L = m->hm.L;
+  fill_level_begin(m->hm, t.lev_begin);
+  t.tau = f.tau;
+  HIPCHK(launch_trace_init(m->ref.N, t, m->stream));
+  return DGRTM_OK;
+}
+
+static dgrtm_status zero_field(dgrtm_shot sh, Field &f) {
+  dgrtm_mesh m = sh->mesh;
+  const int Np = m->ref.Np, F = 4 * m->ref.Nfp;
+  const int64_t K = m->hm.Ktot;
+  HIPCHK(launch_fill_f32(f.q, 4LL * Np * K, 0.0f, m->stream));
+  HIPCHK(launch_fill_f32(f.ring, 12LL * Np * K, 0.0f, m->stream));
+  HIPCHK(launch_fill_f32(f.tr, 6LL * F * K, 0.0f, m->stream));
+  f.tau = 0;
+  return DGRTM_OK;
+}
+
+// one local step of a field: a is prepared by the caller except tau / k_end
+static dgrtm_status local_step(dgrtm_shot sh, Field &f, StepArgs &a) {
+  dgrtm_mesh m = sh->mesh;
+  a.tau = f.tau;
+  a.k_end = active_end(m->hm, f.tau);
+  HIPCHK(launch_step(m->ref.N, a, m->stream));
+  f.tau += 1;
+  return DGRTM_OK;
+}
+
+static void set_source(StepArgs &a, const PointSet &p, int amp_mode) {
+  a.eflag = p.eflag;
+  a.src_start = p.start;
+  a.src_count = p.count;
+  a.src_point = p.point;
+  a.src_w = p.w;
+  a.amp_mode = amp_mode;
+  a.src_scale = 1.0f;
+}
+
+static dgrtm_status record(dgrtm_shot sh, Field &f, int64_t g) {
+  dgrtm_mesh m = sh->mesh;
+  HIPCHK(launch_record(m->ref.N, f.q, m->hm.Ktot, sh->rec.pos, sh->rec.interp, sh->rec.n, sh->traces + g,
+                       sh->n_global + 1, m->stream));
+  return DGRTM_OK;
+}
+
+// checkpoint c = state at the start of global step c*C: q and the two newest rhs of every level
+static dgrtm_status ckpt_copy(dgrtm_shot sh, Field &f, int64_t c, bool save) {
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  const int Np = m->ref.Np;
+  const int64_t K = h.Ktot, slab = 4LL * Np * K;
+  float *ck = sh->ckpt + c * 3 * slab;
+  const int64_t g = c * sh->C;
+  hipStream_t st = m->stream;
+  if (save) HIPCHK(hipMemcpyAsync(ck, f.q, slab * 4, hipMemcpyDeviceToDevice, st));
+  else HIPCHK(hipMemcpyAsync(f.q, ck, slab * 4, hipMemcpyDeviceToDevice, st));
+  for (int l = 1; l <= h.L; ++l) {
+    const int64_t mstep = g << (l - 1);
+    const int64_t b0 = h.lev_begin[l - 1], P = level_size_h(h, l);
+    if (P == 0) continue;
+    for (int s = 1; s <= 2; ++s) {
+      const int64_t slot = ((mstep - s) % 3 + 3) % 3;
+      float *ring = f.ring + slot * slab + b0;
+      float *cks = ck + s * slab + b0;
+      if (save)
+        HIPCHK(hipMemcpy2DAsync(cks, K * 4, ring, K * 4, P * 4, 4 * Np, hipMemcpyDeviceToDevice, st));
+      else
+        HIPCHK(hipMemcpy2DAsync(ring, K * 4, cks, K * 4, P * 4, 4 * Np, hipMemcpyDeviceToDevice, st));
+    }
+  }
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_forward(dgrtm_shot sh, float *traces_out) {
+  if (!sh) return fail(DGRTM_ERR_ARG, "dgrtm_forward: bad argument");
+  dgrtm_mesh m = sh->mesh;
+  dgrtm_status s;
+  if ((s = zero_field(sh, sh->S))) return s;
+  StepArgs a = base_args(sh, sh->S, false);
+  set_source(a, sh->src, 0);
+  a.wavelet = sh->wavelet;
+  if (!sh->args.has_source) a.eflag = m->eflag;
+  if ((s = record(sh, sh->S, 0))) return s;
+  for (int64_t g = 0; g < sh->n_global; ++g) {
+    if (g % sh->C == 0 && (s = ckpt_copy(sh, sh->S, g / sh->C, true))) return s;
+    for (int n = 0; n < sh->n_local; ++n)
+      if ((s = local_step(sh, sh->S, a))) return s;
+    if ((s = record(sh, sh->S, g + 1))) return s;
+  }
+  if (traces_out && sh->rec.n)
+    HIPCHK(hipMemcpyAsync(traces_out, sh->traces, sh->rec.n * (sh->n_global + 1) * 4, hipMemcpyDeviceToDevice,
+                          m->stream));
+  sh->forward_done = true;
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_adjoint(dgrtm_shot sh, const float *data, int condition, const double *up,
+                                      int64_t g_image_start) {
+  if (!sh || (sh->rec.n && !data) || !up) return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: bad argument");
+  if (!sh->forward_done) return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: run dgrtm_forward first");
+  if (condition != DGRTM_IMAGE_PRESSURE && condition != DGRTM_IMAGE_CHARACTERISTIC)
+    return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: bad condition");
+  if (g_image_start < 0 || g_image_start >= sh->n_global) return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: bad g_image_start");
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  const int Np = m->ref.Np;
+  const int64_t K = h.Ktot, NG = sh->n_global, NL = sh->n_local, C = sh->C;
+  dgrtm_status s;
+  HIPCHK(launch_fill_f64(sh->img, (int64_t)Np * K, 0.0, m->stream));
+  if ((s = zero_field(sh, sh->R))) return s;
+  const float upf[3] = {(float)up[0], (float)up[1], (float)up[2]};
+
+  StepArgs as = base_args(sh, sh->S, false);
+  set_source(as, sh->src, 0);
+  as.wavelet = sh->wavelet;
+  if (!sh->args.has_source) as.eflag = m->eflag;
+  as.seg_q = sh->seg_q;
+  as.seg_r = sh->seg_r;
+  as.condition = condition;
+  std::memcpy(as.up, upf, sizeof(upf));
+
+  StepArgs ar = base_args(sh, sh->R, true);
+  set_source(ar, sh->rec, 1);
+  if (!sh->rec.n) ar.eflag = m->eflag;
+  ar.data = data;
+  ar.n_t = NG + 1;
+  ar.src_scale = -1.0f;
+  ar.seg_q = sh->seg_q;
+  ar.seg_r = sh->seg_r;
+  ar.img = sh->img;
+  ar.condition = condition;
+  std::memcpy(ar.up, upf, sizeof(upf));
+  ar.image_from = g_image_start * NL;
+  for (int l = 1; l <= h.L; ++l) {
+    as.seg_q_off[l - 1] = ar.seg_q_off[l - 1] = sh->seg_q_off[l - 1];
+    as.seg_r_off[l - 1] = ar.seg_r_off[l - 1] = sh->seg_r_off[l - 1];
+    ar.own_total[l - 1] = NG << (l - 1);
+  }
+  for (int64_t c = (NG - 1) / C; c >= g_image_start / C; --c) {
+    const int64_t g0 = c * C, g1 = std::min(NG, g0 + C);
+    // restore S at g0 and recompute it over [g0, g1), recording q-_S and r-_S per element-step
+    if ((s = ckpt_copy(sh, sh->S, c, false))) return s;
+    sh->S.tau = g0 * NL;
+    if ((s = trace_init(sh, sh->S))) return s;
+    SegInitArgs si;
+    std::memset(&si, 0, sizeof(si));
+    si.ring = sh->S.ring;
+    si.geo = m->geo;
+    si.eflag = m->eflag;
+    si.seg_r = sh->seg_r;
+    si.Ktot = K;
+    si.L = h.L;
+    fill_level_begin(h, si.lev_begin);
+    std::memcpy(si.up, upf, sizeof(upf));
+    si.condition = condition;
+    for (int l = 1; l <= h.L; ++l) {
+      si.seg_r_off[l - 1] = sh->seg_r_off[l - 1];
+      si.seg_m0[l - 1] = as.seg_m0[l - 1] = ar.seg_m0[l - 1] = g0 << (l - 1);
+      as.seg_len[l - 1] = ar.seg_len[l - 1] = (g1 - g0) << (l - 1);
+    }
+    HIPCHK(launch_seg_init(m->ref.N, si, m->stream));
+    for (int64_t g = g0; g < g1; ++g)
+      for (int n = 0; n < NL; ++n)
+        if ((s = local_step(sh, sh->S, as))) return s;
+    // R backward over the same time span, imaging as it goes
+    const int64_t gr0 = NG - g1, gr1 = NG - std::max(g0, g_image_start);
+    for (int64_t gr = gr0; gr < gr1; ++gr)
+      for (int n = 0; n < NL; ++n) {
+        ar.data_j = NG * NL - sh->R.tau;
+        if ((s = local_step(sh, sh->R, ar))) return s;
+      }
+  }
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_image(dgrtm_shot sh, double *image_out, int accumulate) {
+  if (!sh || !image_out) return fail(DGRTM_ERR_ARG, "dgrtm_image: bad argument");
+  dgrtm_mesh m = sh->mesh;
+  HIPCHK(launch_image_to_user(m->ref.Np, sh->img, image_out, m->s2u, m->hm.Ktot, accumulate, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_residual(dgrtm_shot sh, const float *a, const float *b, int64_t n, double *out) {
+  if (!sh || !a || !b || !out || n < 0) return fail(DGRTM_ERR_ARG, "dgrtm_residual: bad argument");
+  dgrtm_mesh m = sh->mesh;
+  HIPCHK(launch_fill_f64(sh->red, 1, 0.0, m->stream));
+  HIPCHK(launch_residual(a, b, n, sh->red, m->stream));
+  HIPCHK(hipMemcpyAsync(out, sh->red, 8, hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return DGRTM_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// test hooks
+// ------------------------------------------------------------------------------------------------
+extern "C" dgrtm_status dgrtm_apply_rhs(dgrtm_shot sh, const float *q, float *rhs, int reversed) {
+  if (!sh || !q || !rhs) return fail(DGRTM_ERR_ARG, "dgrtm_apply_rhs: bad argument");
+  dgrtm_mesh m = sh->mesh;
+  const int Np = m->ref.Np;
+  const int64_t K = m->hm.Ktot;
+  dgrtm_status s;
+  if ((s = zero_field(sh, sh->S))) return s;
+  HIPCHK(launch_to_device_layout(Np, 4, q, sh->S.q, m->s2u, K, m->stream));
+  if ((s = trace_init(sh, sh->S))) return s;
+  StepArgs a = base_args(sh, sh->S, reversed != 0);
+  a.rhs_out = sh->S.ring;
+  a.tau = 0;
+  a.k_end = K;
+  HIPCHK(launch_step(m->ref.N, a, m->stream));
+  HIPCHK(launch_to_user_layout(Np, 4, sh->S.ring, rhs, m->s2u, K, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_set_state(dgrtm_shot sh, int which, const float *q, const float *h1, const float *h2) {
+  if (!sh || (which != 0 && which != 1)) return fail(DGRTM_ERR_ARG, "dgrtm_set_state: bad argument");
+  dgrtm_mesh m = sh->mesh;
+  const int Np = m->ref.Np;
+  const int64_t K = m->hm.Ktot, slab = 4LL * Np * K;
+  Field &f = which ? sh->R : sh->S;
+  dgrtm_status s;
+  if ((s = zero_field(sh, f))) return s;
+  if (q) HIPCHK(launch_to_device_layout(Np, 4, q, f.q, m->s2u, K, m->stream));
+  // at tau = 0 every element is at own step 0: r(-dt) lives in slot 2, r(-2 dt) in slot 1
+  if (h1) HIPCHK(launch_to_device_layout(Np, 4, h1, f.ring + 2 * slab, m->s2u, K, m->stream));
+  if (h2) HIPCHK(launch_to_device_layout(Np, 4, h2, f.ring + 1 * slab, m->s2u, K, m->stream));
+  if ((s = trace_init(sh, f))) return s;
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_get_state(dgrtm_shot sh, int which, float *q) {
+  if (!sh || !q || (which != 0 && which != 1)) return fail(DGRTM_ERR_ARG, "dgrtm_get_state: bad argument");
+  dgrtm_mesh m = sh->mesh;
+  Field &f = which ? sh->R : sh->S;
+  HIPCHK(launch_to_user_layout(m->ref.Np, 4, f.q, q, m->s2u, m->hm.Ktot, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_run(dgrtm_shot sh, int which, int64_t n_global, int reversed, int with_source) {
+  if (!sh || n_global < 0 || (which != 0 && which != 1)) return fail(DGRTM_ERR_ARG, "dgrtm_run: bad argument");
+  dgrtm_mesh m = sh->mesh;
+  Field &f = which ? sh->R : sh->S;
+  StepArgs a = base_args(sh, f, reversed != 0);
+  if (with_source && which == 0 && sh->args.has_source) {
+    set_source(a, sh->src, 0);
+    a.wavelet = sh->wavelet;
+    if (f.tau + n_global * sh->n_local > sh->n_global * sh->n_local)
+      return fail(DGRTM_ERR_ARG, "dgrtm_run: source signal shorter than the run");
+  }
+  dgrtm_status s;
+  for (int64_t g = 0; g < n_global; ++g)
+    for (int n = 0; n < sh->n_local; ++n)
+      if ((s = local_step(sh, f, a))) return s;
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return DGRTM_OK;
+}

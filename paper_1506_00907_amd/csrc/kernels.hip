@@ -1,0 +1,676 @@
+// gfx950 kernels of the nodal DG solver: fused right-hand side + multi-rate AB3 update per
+// local step (with optional source-wavefield recording and FP64 image accumulation), trace
+// initialisation, receiver sampling, layout conversion and FP64 reductions.
+//
+// One lane owns one element (64 elements per wavefront); all field arrays are node-major
+// with the element index fastest, so every load and store of q, the rhs ring and the trace
+// copies is coalesced across the wavefront.  The reference operators are the same for every
+// lane: their addresses are wavefront-uniform and are served by scalar loads.
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace dgrtm {
+
+// ------------------------------------------------------------------------------------------
+// compile-time node tables of the order-N reference tetrahedron (same numbering as the host:
+// node (i,j,l) has barycentric weights (N-i-j-l, i, j, l), l slowest, i fastest)
+// ------------------------------------------------------------------------------------------
+template <int N>
+struct Tab {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  int fmask[4][Nfp];
+  int fidx[Np][4];  // position of node n on face f, -1 if not on it
+  constexpr Tab() : fmask{}, fidx{} {
+    int lat[Np][4] = {};
+    int n = 0;
+    for (int l = 0; l <= N; ++l)
+      for (int j = 0; j <= N - l; ++j)
+        for (int i = 0; i <= N - l - j; ++i) {
+          lat[n][0] = N - i - j - l;
+          lat[n][1] = i;
+          lat[n][2] = j;
+          lat[n][3] = l;
+          ++n;
+        }
+    const int opp[4] = {3, 2, 0, 1};
+    for (int m = 0; m < Np; ++m)
+      for (int f = 0; f < 4; ++f) fidx[m][f] = -1;
+    for (int f = 0; f < 4; ++f) {
+      int c = 0;
+      for (int m = 0; m < Np; ++m)
+        if (lat[m][opp[f]] == 0) {
+          fmask[f][c] = m;
+          fidx[m][f] = c;
+          ++c;
+        }
+    }
+  }
+};
+
+template <int N>
+struct Dims {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  static constexpr int F = 4 * Nfp;
+  static constexpr int NR = (Np + 15) / 16;   // 16-row tiles of the operators
+  static constexpr int NK = (Np + 3) / 4;     // 4-column chunks of D_j
+  static constexpr int FC = (Nfp + 3) / 4;    // 4-column chunks per face of LIFT
+  static constexpr int OPS = (3 * NR * NK + NR * 4 * FC) * 64;   // operator fragment floats
+};
+
+// AB3 weights of the full step and of the half step, image weights for the mixed-direction
+// correlation (S forward from t_a, R backward from t_b): ebar_s = int_0^1 A_s,
+// Cmix_{s1 s2} = int_0^1 A_s1(th) A_s2(1-th), with A_s = int_0^th of the Lagrange basis on {0,-1,-2}
+constexpr float kA0 = 23.0f / 12.0f, kA1 = -16.0f / 12.0f, kA2 = 5.0f / 12.0f;
+constexpr float kB0 = 17.0f / 24.0f, kB1 = -7.0f / 24.0f, kB2 = 2.0f / 24.0f;
+constexpr double kE[3] = {19.0 / 24.0, -5.0 / 12.0, 1.0 / 8.0};
+constexpr double kCm[3][3] = {{3341.0 / 10080.0, -667.0 / 5040.0, 43.0 / 1120.0},
+                              {-667.0 / 5040.0, 19.0 / 420.0, -13.0 / 1008.0},
+                              {43.0 / 1120.0, -13.0 / 1008.0, 37.0 / 10080.0}};
+
+__device__ __forceinline__ int level_of(const int64_t *lev_begin, int L, int64_t k) {
+  // segments are stored finest first, so starts decrease with the level number
+  for (int l = 1; l < L; ++l)
+    if (k >= lev_begin[l - 1]) return l;
+  return L;
+}
+
+__device__ __forceinline__ int64_t level_end(const int64_t *lev_begin, int L, int l) {
+  return l == 1 ? lev_begin[L] : lev_begin[l - 2];
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// select one of four compile-time constants by the lane group g = lane / 16
+__device__ __forceinline__ int sel4(int g, int a, int b, int c, int d) {
+  return g == 0 ? a : (g == 1 ? b : (g == 2 ? c : d));
+}
+
+// One wavefront owns a tile of 16 consecutive elements.  The element-batched operator products
+// run on v_mfma_f32_16x16x4_f32: A = 16 operator rows x 4 columns (lane l holds
+// A[l%16][l/16]), B = 4 input nodes x 16 elements (lane l holds B[l/16][l%16]), C = 16 rows x 16
+// elements (lane l holds rows 4(l/16)+i, i=0..3, of element l%16).  All elementwise work
+// (geometric factors, penalties, AB3, traces, image) runs in that C layout: lane l handles the
+// element e = l%16 and, in row tile rt, the nodes n = 16 rt + 4 (l/16) + i.
+template <int N, int MODE, bool OPS_LDS>
+__global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
+  constexpr Tab<N> T{};
+  using Dm = Dims<N>;
+  constexpr int Np = Dm::Np, Nfp = Dm::Nfp, F = Dm::F, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
+  extern __shared__ float sops[];
+  const float *ops = a.ops;
+  if constexpr (OPS_LDS) {
+    for (int i = threadIdx.x; i < Dm::OPS; i += blockDim.x) sops[i] = a.ops[i];
+    __syncthreads();
+    ops = sops;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = lane & 15, g = lane >> 4;
+  const int64_t K = a.Ktot;
+  const int64_t ntiles = a.k_end >> 4;
+  const int64_t slab = (int64_t)4 * Np * K;
+
+  for (int64_t grp = blockIdx.x; grp * 4 < ntiles; grp += gridDim.x) {
+    const int64_t tile = grp * 4 + wave;
+    if (tile >= ntiles) continue;
+    const int64_t k = tile * 16 + e;
+    // an opaque zero keeps the operator-fragment reads inside the tile loop (hoisting them out
+    // would pin every fragment in registers for the whole kernel)
+    int opaque0;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
+    const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
+    const float *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;    // [NR][4*FC][64]
+    const int flag = a.eflag[k];
+    const bool valid = (flag & 1) != 0;
+    const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
+    const int sh = a.L - lev;
+    const int64_t m = a.tau >> sh;
+
+    float gg[kGeo];
+#pragma unroll
+    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[i * K + k];
+    const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
+                tz = gg[8];
+    const float rc2 = gg[9], irho = gg[10], Z = gg[11];
+    const float *__restrict__ q0 = a.q;
+    const float *__restrict__ q1 = a.q + (int64_t)Np * K;
+    const float *__restrict__ q2 = a.q + (int64_t)2 * Np * K;
+    const float *__restrict__ q3 = a.q + (int64_t)3 * Np * K;
+
+    // ---- volume: Cp = sum_j D_j U_j and W_j = D_j p
+    v4f cp[NR], w0[NR], w1[NR], w2[NR];
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int c = 0; c < NK; ++c) {
+      const int mm = 4 * c + g;
+      float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+      if (mm < Np) {
+        p = q0[mm * K + k]; vx = q1[mm * K + k]; vy = q2[mm * K + k]; vz = q3[mm * K + k];
+      }
+      const float Ur = rx * vx + ry * vy + rz * vz;
+      const float Us = sx * vx + sy * vy + sz * vz;
+      const float Ut = tx * vx + ty * vy + tz * vz;
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt) {
+        const float ar = fD[((0 * NR + rt) * NK + c) * 64 + lane];
+        const float as = fD[((1 * NR + rt) * NK + c) * 64 + lane];
+        const float at = fD[((2 * NR + rt) * NK + c) * 64 + lane];
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, Ur, cp[rt], 0, 0, 0);
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, Us, cp[rt], 0, 0, 0);
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Ut, cp[rt], 0, 0, 0);
+        w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, p, w0[rt], 0, 0, 0);
+        w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, p, w1[rt], 0, 0, 0);
+        w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, p, w2[rt], 0, 0, 0);
+      }
+    }
+    v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float wr = w0[rt][i], ws = w1[rt][i], wt = w2[rt][i];
+        rp[rt][i] = -rc2 * cp[rt][i];
+        rvx[rt][i] = -irho * (rx * wr + sx * ws + tx * wt);
+        rvy[rt][i] = -irho * (ry * wr + sy * ws + ty * wt);
+        rvz[rt][i] = -irho * (rz * wr + sz * ws + tz * wt);
+      }
+
+    // ---- surface: rp -= LIFT Pp (accumulated by the MFMA with -Pp), G_f = LIFT_f Pv, rv -= n_f G_f
+    float nfx[4], nfy[4], nfz[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      float nx, ny, nz;
+      if (f == 0) { nx = -tx; ny = -ty; nz = -tz; }
+      else if (f == 1) { nx = -sx; ny = -sy; nz = -sz; }
+      else if (f == 2) { nx = rx + sx + tx; ny = ry + sy + ty; nz = rz + sz + tz; }
+      else { nx = -rx; ny = -ry; nz = -rz; }
+      const float Fs = sqrtf(nx * nx + ny * ny + nz * nz);
+      const float inv = 1.0f / Fs;
+      nx *= inv; ny *= inv; nz *= inv;
+      nfx[f] = nx; nfy[f] = ny; nfz[f] = nz;
+      const int nb = a.nbr[f * K + k];
+      const int code = a.ncode[f * K + k];
+      const float taup = a.tau_sign * gg[12 + f], tauv = a.tau_sign * gg[16 + f];
+      const float *trp = a.tr;
+      const int8_t *tab = a.nbr_index;
+      int f2 = 0;
+      if (nb >= 0) {
+        f2 = code & 3;
+        const int perm = (code >> 2) & 7;
+        const int shn = a.L - (code >> 5);
+        const int slot = ((a.tau & ((1LL << shn) - 1)) == 0) ? (int)((a.tau >> shn) & 1) : 2;
+        trp = a.tr + (int64_t)slot * 2 * F * K;
+        tab = a.nbr_index + ((f * 4 + f2) * 6 + perm) * Nfp;
+      }
+      v4f G[NR];
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int cc = 0; cc < FC; ++cc) {
+        const int s = 4 * cc + g;   // face node handled by this lane in this chunk
+        float Pp = 0.f, Pv = 0.f;
+        if (4 * cc + 3 < Nfp || s < Nfp) {
+          const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
+                                T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
+          const float pm = q0[node * K + k];
+          const float nvm = nx * q1[node * K + k] + ny * q2[node * K + k] + nz * q3[node * K + k];
+          float pp, nvp;
+          if (nb >= 0) {
+            const int64_t row = f2 * Nfp + tab[s];
+            pp = trp[row * K + nb];
+            nvp = -trp[(F + row) * K + nb];
+          } else if (nb == -1) {  // rigid wall
+            pp = pm;
+            nvp = -nvm;
+          } else if (nb == -2) {  // transparent
+            pp = 0.0f;
+            nvp = 0.0f;
+          } else {  // free surface
+            pp = -pm;
+            nvp = nvm;
+          }
+          const float dp = pp - pm, dnv = nvp - nvm;
+          Pp = -0.5f * rc2 * (dnv - taup * dp) * Fs;
+          Pv = 0.5f * irho * (dp - tauv * dnv) * Fs;
+        }
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt) {
+          const float al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
+          rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pp, rp[rt], 0, 0, 0);
+          G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          rvx[rt][i] -= nx * G[rt][i];
+          rvy[rt][i] -= ny * G[rt][i];
+          rvz[rt][i] -= nz * G[rt][i];
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (a.out_sign < 0.0f) {
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt) {
+        rp[rt] = -rp[rt]; rvx[rt] = -rvx[rt]; rvy[rt] = -rvy[rt]; rvz[rt] = -rvz[rt];
+      }
+    }
+
+    // ---- point sources (projected delta into the pressure equation)
+    if (valid && (flag & 4)) {
+      const int s0 = a.src_start[k], scn = a.src_count[k];
+      for (int en = s0; en < s0 + scn; ++en) {
+        const int pt = a.src_point[en];
+        float amp = 0.0f;
+        if (a.amp_mode == 0) {
+          amp = a.wavelet[a.tau];
+        } else {
+          const int64_t j = a.data_j;
+          const int64_t gq = j / a.n_local, rem = j % a.n_local;
+          if (j >= 0 && (gq < a.n_t - 1 || (gq == a.n_t - 1 && rem == 0))) {
+            const float *d = a.data + (int64_t)pt * a.n_t;
+            if (rem == 0) amp = d[gq];
+            else {
+              const float th = (float)rem / (float)a.n_local;
+              amp = (1.0f - th) * d[gq] + th * d[gq + 1];
+            }
+          }
+        }
+        amp *= a.src_scale;
+        const float *w = a.src_w + (int64_t)pt * Np;
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int n = 16 * rt + 4 * g + i;
+            if (16 * rt + 15 < Np || n < Np) rp[rt][i] += amp * w[n];
+          }
+      }
+    }
+
+    if constexpr (MODE == MODE_RHS_ONLY) {
+      if (valid) {
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int n = 16 * rt + 4 * g + i;
+            if (16 * rt + 15 < Np || n < Np) {
+              a.rhs_out[(int64_t)(0 * Np + n) * K + k] = rp[rt][i];
+              a.rhs_out[(int64_t)(1 * Np + n) * K + k] = rvx[rt][i];
+              a.rhs_out[(int64_t)(2 * Np + n) * K + k] = rvy[rt][i];
+              a.rhs_out[(int64_t)(3 * Np + n) * K + k] = rvz[rt][i];
+            }
+          }
+      }
+      continue;
+    }
+
+    // ---- AB3 update, rhs ring, traces of the new state (and of the half step for coarse neighbours)
+    const float dtl = (float)(a.dt_local * (double)(1LL << sh));
+    float *__restrict__ R0 = a.ring + (m % 3) * slab;
+    const float *__restrict__ R1 = a.ring + ((m + 2) % 3) * slab;
+    const float *__restrict__ R2 = a.ring + ((m + 1) % 3) * slab;
+    float *__restrict__ trw = a.tr + ((m + 1) & 1) * (int64_t)2 * F * K;
+    float *__restrict__ trm = a.tr + (int64_t)2 * 2 * F * K;
+    const bool mid = (flag & 2) != 0;
+    float *q = a.q;
+    const float ux = a.up[0], uy = a.up[1], uz = a.up[2];
+    const float zs = a.condition ? Z : 0.0f;
+    int64_t kk = 0, Pl = 0, jS = 0;
+    bool do_img = false;
+    if constexpr (MODE == MODE_RECORD_SEG || MODE == MODE_IMAGE) {
+      kk = k - a.lev_begin[lev - 1];
+      Pl = level_end(a.lev_begin, a.L, lev) - a.lev_begin[lev - 1];
+    }
+    if constexpr (MODE == MODE_RECORD_SEG) jS = m - a.seg_m0[lev - 1];
+    if constexpr (MODE == MODE_IMAGE) {
+      const int64_t mS = a.own_total[lev - 1] - m - 1;
+      jS = mS - a.seg_m0[lev - 1];
+      do_img = (mS << sh) >= a.image_from && jS >= 0 && jS < a.seg_len[lev - 1];
+    }
+    const double dtd = a.dt_local * (double)(1LL << sh);
+    if (!valid) continue;
+
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = 16 * rt + 4 * g + i;
+        if (!(16 * rt + 15 < Np || n < Np)) continue;
+        const float r[4] = {rp[rt][i], rvx[rt][i], rvy[rt][i], rvz[rt][i]};
+        float qo[4], h1[4], h2[4], qn[4], qm[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t idx = (int64_t)(c * Np + n) * K + k;
+          h1[c] = R1[idx];
+          h2[c] = R2[idx];
+          qo[c] = q[idx];
+          R0[idx] = r[c];
+          qn[c] = qo[c] + dtl * (kA0 * r[c] + kA1 * h1[c] + kA2 * h2[c]);
+          q[idx] = qn[c];
+          qm[c] = qo[c] + dtl * (kB0 * r[c] + kB1 * h1[c] + kB2 * h2[c]);
+        }
+        if constexpr (MODE == MODE_RECORD_SEG) {
+          const float qminus = qo[0] - zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
+          const float rminus = r[0] - zs * (ux * r[1] + uy * r[2] + uz * r[3]);
+          a.seg_q[a.seg_q_off[lev - 1] + (jS * Np + n) * Pl + kk] = qminus;
+          a.seg_r[a.seg_r_off[lev - 1] + ((jS + 2) * Np + n) * Pl + kk] = rminus;
+        }
+        if constexpr (MODE == MODE_IMAGE) {
+          if (do_img) {
+            const float *sq = a.seg_q + a.seg_q_off[lev - 1];
+            const float *sr = a.seg_r + a.seg_r_off[lev - 1];
+            const double qS = sq[(jS * Np + n) * Pl + kk];
+            const double rS[3] = {sr[((jS + 2) * Np + n) * Pl + kk], sr[((jS + 1) * Np + n) * Pl + kk],
+                                  sr[(jS * Np + n) * Pl + kk]};
+            const double qR = qo[0] + zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
+            const double rR[3] = {r[0] + zs * (ux * r[1] + uy * r[2] + uz * r[3]),
+                                  h1[0] + zs * (ux * h1[1] + uy * h1[2] + uz * h1[3]),
+                                  h2[0] + zs * (ux * h2[1] + uy * h2[2] + uz * h2[3])};
+            double inc2 = 0.0, inc3 = 0.0;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) inc2 += kE[s] * (qS * rR[s] + rS[s] * qR);
+#pragma unroll
+            for (int s1 = 0; s1 < 3; ++s1)
+#pragma unroll
+              for (int s2 = 0; s2 < 3; ++s2) inc3 += kCm[s1][s2] * rS[s1] * rR[s2];
+            a.img[(int64_t)n * K + k] += dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int fi = sel4(g, T.fidx[min(16 * rt + i, Np - 1)][f], T.fidx[min(16 * rt + 4 + i, Np - 1)][f],
+                              T.fidx[min(16 * rt + 8 + i, Np - 1)][f], T.fidx[min(16 * rt + 12 + i, Np - 1)][f]);
+          if (fi >= 0) {
+            const int64_t r0 = (int64_t)(f * Nfp + fi) * K + k;
+            const int64_t r1 = (int64_t)(F + f * Nfp + fi) * K + k;
+            trw[r0] = qn[0];
+            trw[r1] = nfx[f] * qn[1] + nfy[f] * qn[2] + nfz[f] * qn[3];
+            if (mid) {
+              trm[r0] = qm[0];
+              trm[r1] = nfx[f] * qm[1] + nfy[f] * qm[2] + nfz[f] * qm[3];
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) {
+  constexpr Tab<N> T{};
+  constexpr int Np = Tab<N>::Np, Nfp = Tab<N>::Nfp, F = 4 * Nfp;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.Ktot) return;
+  const int64_t K = a.Ktot;
+  if (!(a.eflag[k] & 1)) return;
+  const int lev = level_of(a.lev_begin, a.L, k);
+  const int64_t m = a.tau >> (a.L - lev);
+  float *tr = a.tr + (m & 1) * (int64_t)2 * F * K;
+  float g[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) g[i] = a.geo[i * K + k];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    float nx, ny, nz;
+    if (f == 0) { nx = -g[6]; ny = -g[7]; nz = -g[8]; }
+    else if (f == 1) { nx = -g[3]; ny = -g[4]; nz = -g[5]; }
+    else if (f == 2) { nx = g[0] + g[3] + g[6]; ny = g[1] + g[4] + g[7]; nz = g[2] + g[5] + g[8]; }
+    else { nx = -g[0]; ny = -g[1]; nz = -g[2]; }
+    const float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+    nx *= inv; ny *= inv; nz *= inv;
+#pragma unroll
+    for (int i = 0; i < Nfp; ++i) {
+      const int node = T.fmask[f][i];
+      const float p = a.q[(int64_t)node * K + k];
+      const float vx = a.q[(int64_t)(Np + node) * K + k];
+      const float vy = a.q[(int64_t)(2 * Np + node) * K + k];
+      const float vz = a.q[(int64_t)(3 * Np + node) * K + k];
+      tr[(int64_t)(f * Nfp + i) * K + k] = p;
+      tr[(int64_t)(F + f * Nfp + i) * K + k] = nx * vx + ny * vy + nz * vz;
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void seg_init_kernel(const SegInitArgs a) {
+  constexpr int Np = Tab<N>::Np;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.Ktot) return;
+  const int64_t K = a.Ktot;
+  if (!(a.eflag[k] & 1)) return;
+  const int lev = level_of(a.lev_begin, a.L, k);
+  const int64_t kk = k - a.lev_begin[lev - 1];
+  const int64_t Pl = level_end(a.lev_begin, a.L, lev) - a.lev_begin[lev - 1];
+  const int64_t m0 = a.seg_m0[lev - 1];
+  const float zs = a.condition ? a.geo[11 * K + k] : 0.0f;
+  const int64_t slab = (int64_t)4 * Np * K;
+  for (int s = 1; s <= 2; ++s) {
+    const int64_t ms = m0 - s;
+    const float *R = a.ring + ((ms % 3 + 3) % 3) * slab;
+    for (int n = 0; n < Np; ++n) {
+      float v = 0.0f;
+      if (ms >= 0) {
+        const float r0 = R[(int64_t)n * K + k], r1 = R[(int64_t)(Np + n) * K + k];
+        const float r2 = R[(int64_t)(2 * Np + n) * K + k], r3 = R[(int64_t)(3 * Np + n) * K + k];
+        v = r0 - zs * (a.up[0] * r1 + a.up[1] * r2 + a.up[2] * r3);
+      }
+      a.seg_r[a.seg_r_off[lev - 1] + ((2 - s) * Np + n) * Pl + kk] = v;
+    }
+  }
+}
+
+__global__ void record_kernel(const float *q, int64_t K, const int64_t *pos, const float *l, int64_t n_rec, int Np,
+                              float *out, int64_t stride) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rec) return;
+  const int64_t k = pos[r];
+  float acc = 0.0f;
+  for (int n = 0; n < Np; ++n) acc += l[r * Np + n] * q[(int64_t)n * K + k];
+  out[r * stride] = acc;
+}
+
+__global__ void to_dev_kernel(int Np, int nf, const float *user, float *dev, const int64_t *s2u, int64_t K) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * Np) return;
+  const int64_t k = t % K, n = t / K;
+  const int64_t u = s2u[k];
+  for (int c = 0; c < nf; ++c) dev[(c * Np + n) * K + k] = u >= 0 ? user[(u * nf + c) * Np + n] : 0.0f;
+}
+
+__global__ void to_user_kernel(int Np, int nf, const float *dev, float *user, const int64_t *s2u, int64_t K) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * Np) return;
+  const int64_t k = t % K, n = t / K;
+  const int64_t u = s2u[k];
+  if (u < 0) return;
+  for (int c = 0; c < nf; ++c) user[(u * nf + c) * Np + n] = dev[(c * Np + n) * K + k];
+}
+
+__global__ void img_user_kernel(int Np, const double *img, double *user, const int64_t *s2u, int64_t K, int acc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * Np) return;
+  const int64_t k = t % K, n = t / K;
+  const int64_t u = s2u[k];
+  if (u < 0) return;
+  const double v = img[n * K + k];
+  if (acc) user[u * Np + n] += v;
+  else user[u * Np + n] = v;
+}
+
+__global__ void residual_kernel(const float *a, const float *b, int64_t n, double *out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)a[i] - (double)b[i];
+    s += d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+__global__ void fill_f32_kernel(float *p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void fill_f64_kernel(double *p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int N, int MODE>
+static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
+  const int64_t groups = (a.k_end / 16 + 3) / 4;
+  const int64_t cap = a.max_groups > 0 ? a.max_groups : groups;
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, cap))), block(256);
+  constexpr size_t lds = Dims<N>::OPS * sizeof(float);
+  if constexpr (lds <= 96 * 1024) {
+    if constexpr (lds > 64 * 1024) {
+      static bool attr_done = false;
+      if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void *)step_kernel<N, MODE, true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+      }
+    }
+    hipLaunchKernelGGL((step_kernel<N, MODE, true>), grid, block, lds, st, a);
+  } else {
+    hipLaunchKernelGGL((step_kernel<N, MODE, false>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_step_n(const StepArgs &a, hipStream_t st) {
+  if (a.k_end <= 0) return hipSuccess;
+  if (a.rhs_out) return launch_step_mode<N, MODE_RHS_ONLY>(a, st);
+  if (a.img) return launch_step_mode<N, MODE_IMAGE>(a, st);
+  if (a.seg_q) return launch_step_mode<N, MODE_RECORD_SEG>(a, st);
+  return launch_step_mode<N, MODE_PLAIN>(a, st);
+}
+
+// operator fragments in the MFMA A-operand lane order (see step_kernel)
+void build_op_fragments(int N, const float *Dr, const float *Ds, const float *Dt, const float *LIFT, float *out) {
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2, F = 4 * Nfp;
+  const int NR = (Np + 15) / 16, NK = (Np + 3) / 4, FC = (Nfp + 3) / 4;
+  const float *D[3] = {Dr, Ds, Dt};
+  for (int j = 0; j < 3; ++j)
+    for (int rt = 0; rt < NR; ++rt)
+      for (int c = 0; c < NK; ++c)
+        for (int l = 0; l < 64; ++l) {
+          const int row = 16 * rt + (l & 15), col = 4 * c + (l >> 4);
+          out[((j * NR + rt) * NK + c) * 64 + l] = (row < Np && col < Np) ? D[j][row * Np + col] : 0.0f;
+        }
+  float *L = out + 3 * NR * NK * 64;
+  for (int rt = 0; rt < NR; ++rt)
+    for (int f = 0; f < 4; ++f)
+      for (int cc = 0; cc < FC; ++cc)
+        for (int l = 0; l < 64; ++l) {
+          const int row = 16 * rt + (l & 15), s = 4 * cc + (l >> 4);
+          L[(rt * 4 * FC + f * FC + cc) * 64 + l] = (row < Np && s < Nfp) ? LIFT[row * F + f * Nfp + s] : 0.0f;
+        }
+}
+
+int64_t op_fragment_floats(int N) {
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
+  const int NR = (Np + 15) / 16, NK = (Np + 3) / 4, FC = (Nfp + 3) / 4;
+  return (int64_t)(3 * NR * NK + NR * 4 * FC) * 64;
+}
+
+hipError_t launch_step(int N, const StepArgs &a, hipStream_t st) {
+  switch (N) {
+    case 1: return launch_step_n<1>(a, st);
+    case 2: return launch_step_n<2>(a, st);
+    case 3: return launch_step_n<3>(a, st);
+    case 4: return launch_step_n<4>(a, st);
+    case 5: return launch_step_n<5>(a, st);
+    case 6: return launch_step_n<6>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_trace_init(int N, const TraceInitArgs &a, hipStream_t st) {
+  const dim3 grid(blocks_for(a.Ktot, 256)), block(256);
+  switch (N) {
+    case 1: hipLaunchKernelGGL(trace_init_kernel<1>, grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(trace_init_kernel<2>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(trace_init_kernel<3>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(trace_init_kernel<4>, grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL(trace_init_kernel<5>, grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL(trace_init_kernel<6>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_init(int N, const SegInitArgs &a, hipStream_t st) {
+  const dim3 grid(blocks_for(a.Ktot, 256)), block(256);
+  switch (N) {
+    case 1: hipLaunchKernelGGL(seg_init_kernel<1>, grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(seg_init_kernel<2>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(seg_init_kernel<3>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(seg_init_kernel<4>, grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL(seg_init_kernel<5>, grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL(seg_init_kernel<6>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_record(int N, const float *q, int64_t Ktot, const int64_t *rec_pos, const float *rec_l, int64_t n_rec,
+                         float *out, int64_t out_stride, hipStream_t st) {
+  if (n_rec <= 0) return hipSuccess;
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  hipLaunchKernelGGL(record_kernel, dim3(blocks_for(n_rec, 256)), dim3(256), 0, st, q, Ktot, rec_pos, rec_l, n_rec, Np,
+                     out, out_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_device_layout(int Np, int nf, const float *user, float *dev, const int64_t *s2u, int64_t K,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(to_dev_kernel, dim3(blocks_for(K * Np, 256)), dim3(256), 0, st, Np, nf, user, dev, s2u, K);
+  return hipGetLastError();
+}
+hipError_t launch_to_user_layout(int Np, int nf, const float *dev, float *user, const int64_t *s2u, int64_t K,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(to_user_kernel, dim3(blocks_for(K * Np, 256)), dim3(256), 0, st, Np, nf, dev, user, s2u, K);
+  return hipGetLastError();
+}
+hipError_t launch_image_to_user(int Np, const double *img, double *user, const int64_t *s2u, int64_t K, int acc,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(img_user_kernel, dim3(blocks_for(K * Np, 256)), dim3(256), 0, st, Np, img, user, s2u, K, acc);
+  return hipGetLastError();
+}
+hipError_t launch_residual(const float *a, const float *b, int64_t n, double *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  unsigned nb = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(256), 0, st, a, b, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace dgrtm

@@ -1,0 +1,116 @@
+// Launch interface of the gfx950 DG kernels (FP32 state, FP64 image accumulation).
+//
+// Device layout (element index fastest, elements sorted finest level first, each level's
+// segment padded to a multiple of 64 so a wavefront never straddles two levels):
+//   q     [4][Np][Ktot]            p, vx, vy, vz
+//   ring  [3][4][Np][Ktot]         AB3 right-hand-side history, slot = own step index mod 3
+//   tr    [3][2][4*Nfp][Ktot]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step
+//   geo   [kGeo][Ktot]             rx ry rz sx sy sz tx ty tz, rho c^2, 1/rho, Z, tau_p[4], tau_v[4]
+//   nbr   [4][Ktot]                neighbour position, or -(boundary type) on a boundary face
+//   ncode [4][Ktot]                neighbour face | vertex permutation << 2 | neighbour level << 5
+//   eflag [Ktot]                   bit0 real element, bit1 has a finer neighbour, bit2 has sources
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgrtm {
+
+constexpr int kGeo = 20;
+constexpr int kMaxLevels = 8;
+
+enum StepMode : int { MODE_PLAIN = 0, MODE_RECORD_SEG = 1, MODE_IMAGE = 2, MODE_RHS_ONLY = 3 };
+
+struct StepArgs {
+  // mesh
+  const float *geo;
+  const int *nbr;
+  const int *ncode;
+  const int *eflag;
+  const float *ops;                   // operator fragments (build_op_fragments)
+  const int8_t *nbr_index;            // [4][4][6][Nfp]
+  int64_t Ktot;
+  int L;                              // number of levels
+  int64_t lev_begin[kMaxLevels + 1];  // index l-1 -> first position of level l (finest first)
+  // state
+  float *q, *ring, *tr;
+  float *rhs_out;                     // MODE_RHS_ONLY output [4][Np][Ktot]
+  // schedule
+  int64_t tau;                        // local steps since the start of the run
+  int64_t k_end;                      // active prefix (multiple of 64)
+  int64_t max_groups;                 // cap on work-groups (each takes 64 elements per pass); 0 = none
+  double dt_local;
+  float tau_sign;                     // +1 forward, -1 backward in time
+  float out_sign;                     // +1 forward, -1 backward in time
+  // sources: CSR per element (sorted position)
+  const int *src_start;               // [Ktot] first point entry
+  const int *src_count;               // [Ktot]
+  const int *src_point;               // entries -> point id
+  const float *src_w;                 // [n_points][Np] projected-delta weights
+  int amp_mode;                       // 0: wavelet table per local step, 1: linear data interpolation
+  const float *wavelet;               // amp_mode 0: [n_steps] sampled source signal
+  const float *data;                  // amp_mode 1: [n_points][n_t]
+  int64_t n_t;
+  int64_t data_j;                     // physical time of this rhs in local steps (amp_mode 1)
+  int n_local;                        // local steps per global step
+  float src_scale;
+  // segment buffer (S recompute) and image (R backward)
+  float *seg_q, *seg_r;               // per level: [n_seg_l][Np][P_l] and [n_seg_l+2][Np][P_l]
+  int64_t seg_q_off[kMaxLevels], seg_r_off[kMaxLevels];
+  int64_t seg_m0[kMaxLevels];         // first own step of the segment, per level
+  int64_t seg_len[kMaxLevels];        // own steps in the segment, per level
+  int64_t own_total[kMaxLevels];      // own steps of the whole run, per level (image mode)
+  int64_t image_from;                 // image only where the S step starts at or after this local step
+  double *img;                        // [Np][Ktot]
+  float up[3];
+  int condition;                      // 0 pressure, 1 characteristic
+};
+
+hipError_t launch_step(int N, const StepArgs &a, hipStream_t st);
+// operator fragments in MFMA lane order from row-major Dr, Ds, Dt (Np x Np) and LIFT (Np x 4Nfp)
+void build_op_fragments(int N, const float *Dr, const float *Ds, const float *Dt, const float *LIFT, float *out);
+int64_t op_fragment_floats(int N);
+
+struct TraceInitArgs {
+  const float *q;
+  float *tr;
+  const float *geo;
+  const int *eflag;
+  int64_t Ktot;
+  int L;
+  int64_t lev_begin[kMaxLevels + 1];
+  int64_t tau;
+};
+hipError_t launch_trace_init(int N, const TraceInitArgs &a, hipStream_t st);
+
+// receivers: out[r * out_stride] = l_r . p(element of r)
+hipError_t launch_record(int N, const float *q, int64_t Ktot, const int64_t *rec_pos, const float *rec_l, int64_t n_rec,
+                         float *out, int64_t out_stride, hipStream_t st);
+// layout conversion user [K][4][Np] <-> device [4][Np][Ktot]
+hipError_t launch_to_device_layout(int Np, int nfield, const float *user, float *dev, const int64_t *sorted_to_user,
+                                   int64_t Ktot, hipStream_t st);
+hipError_t launch_to_user_layout(int Np, int nfield, const float *dev, float *user, const int64_t *sorted_to_user,
+                                 int64_t Ktot, hipStream_t st);
+hipError_t launch_image_to_user(int Np, const double *img, double *user, const int64_t *sorted_to_user, int64_t Ktot,
+                                int accumulate, hipStream_t st);
+// r-_S history entries of the segment buffer from the ring at restore time
+struct SegInitArgs {
+  const float *ring;
+  const float *geo;
+  const int *eflag;
+  float *seg_r;
+  int64_t seg_r_off[kMaxLevels];
+  int64_t seg_m0[kMaxLevels];
+  int64_t Ktot;
+  int L;
+  int64_t lev_begin[kMaxLevels + 1];
+  float up[3];
+  int condition;
+};
+hipError_t launch_seg_init(int N, const SegInitArgs &a, hipStream_t st);
+// sum over all entries of (a - b)^2 in FP64 into out[0] (out zeroed by the caller)
+hipError_t launch_residual(const float *a, const float *b, int64_t n, double *out, hipStream_t st);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
+
+}  // namespace dgrtm

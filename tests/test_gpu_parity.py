@@ -1,0 +1,139 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP32 fields <= 1e-5 relative L2 after 100 steps, images <= 1e-4 relative L2;
+one rhs application <= 2e-6 (a single FP32 operator evaluation)."""
+import numpy as np
+import pytest
+
+from oracle import source as OS
+from oracle import timestep as T
+from oracle.mesh import BC_FREE, BC_RIGID, BC_TRANSPARENT, OMesh, local_dt, lts_levels
+from oracle.rtm import COND_CHARACTERISTIC, COND_PRESSURE, Shot as OShot
+from oracle.refelem import get_ref
+from paper_1506_00907_amd import inputs as I
+from tests.oracle_cases import case, eigenmode
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def lib_mesh(name, bc, nl, face_bc=None, rho=None, c=None):
+    from paper_1506_00907_amd import dgrtm
+    mm, rho0, c0, N = I.config_mesh(name)
+    rho = rho0 if rho is None else rho
+    c = c0 if c is None else c
+    m = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=bc, face_bc=face_bc).set_model(rho, c, n_levels_max=nl)
+    return m.bind("cuda"), mm, rho, c, N
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("name", ["two_layer_small:4:4:3:3", "two_layer_small:4:3:3:4", "two_layer_small:3:3:2:5",
+                                  "two_layer_small:3:2:2:2", "two_layer_small:2:2:2:1"])
+@pytest.mark.parametrize("reversed_time", [False, True])
+def test_rhs_parity_mixed_boundaries(name, reversed_time):
+    from paper_1506_00907_amd import dgrtm
+    mm, rho, c, N = I.config_mesh(name)
+    rng = np.random.default_rng(11)
+    rho = rho * rng.uniform(0.8, 1.5, mm.K)
+    bc = rng.choice([BC_RIGID, BC_TRANSPARENT, BC_FREE], size=(mm.K, 4)).astype(np.int8)
+    lm = dgrtm.Mesh(N, mm.verts, mm.etov, face_bc=bc).set_model(rho, c, n_levels_max=3).bind("cuda")
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=lm.dt_local))
+    om = OMesh(get_ref(N), mm.verts, mm.etov, face_bc=bc)
+    from oracle.dg import Operator
+    op = Operator(om, rho, c)
+    q = rng.standard_normal((mm.K, 4, lm.Np))
+    got = shot.apply_rhs(dev(q), reversed_time=reversed_time).cpu().numpy()
+    ref = op.rhs_reversed(q) if reversed_time else op.rhs(q)
+    assert rel(got, ref) < 2e-6
+
+
+def test_single_rate_ab3_eigenmode_100_steps():
+    from paper_1506_00907_amd import dgrtm
+    lm, mm, rho, c, N = lib_mesh("eigen_cube", BC_RIGID, 1)
+    m, op, lev, L, dtl = case("eigen_cube", bc=BC_RIGID, n_levels=1)
+    assert lm.dt_local == dtl and lm.L == 1
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=100 * dtl))
+    M = op.m
+    q0 = eigenmode(M, 0.0)
+    h1, h2 = op.rhs(eigenmode(M, -dtl)), op.rhs(eigenmode(M, -2 * dtl))
+    shot.set_state(dgrtm.SOURCE_FIELD, dev(q0), dev(h1), dev(h2))
+    shot.run(dgrtm.SOURCE_FIELD, 100)
+    got = shot.get_state(dgrtm.SOURCE_FIELD).cpu().numpy()
+    ref, _ = T.ab3(op, q0, dtl, 100, hist=np.stack([h1, h2]))
+    assert rel(got, ref) < 1e-5
+    # and the closed form is met to the discretisation error
+    e = np.sqrt(op.energy(got - eigenmode(M, 100 * dtl)) / op.energy(q0))
+    assert e < 2e-4
+
+
+def _oracle_shot(name, lev, L, dtl, op, n_global, spec):
+    M = op.m
+    se = OS.locate(M, spec.src[None])[0]
+    sw = OS.delta_weights(M, np.array([se]), spec.src[None])[0]
+    re = OS.locate(M, spec.rec)
+    return OShot(op, lev, L, dtl, n_global, se, sw, lambda t: OS.ricker(t, spec.f_peak, spec.t_peak), re,
+                 OS.interp_rows(M, re, spec.rec), OS.delta_weights(M, re, spec.rec))
+
+
+@pytest.mark.parametrize("name,nl", [("two_layer_small:6:6:4:3", 3), ("two_layer_small:5:5:3:4", 3)])
+def test_multirate_forward_fields_and_traces(name, nl):
+    from paper_1506_00907_amd import dgrtm
+    lm, mm, rho, c, N = lib_mesh(name, BC_TRANSPARENT, nl)
+    m, op, lev, L, dtl = case(name, bc=BC_TRANSPARENT, n_levels=nl)
+    assert L == lm.L and L >= 2
+    spec = I.rtm_shot(n_rec=5)
+    ng = 100 // (2 ** (L - 1)) + 1
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=ng * dtl * 2 ** (L - 1), src=spec.src, f_peak=spec.f_peak,
+                                         t_peak=0.02, rec=spec.rec))
+    assert shot.n_global == ng
+    tr = shot.forward().cpu().numpy()
+    q = shot.get_state(dgrtm.SOURCE_FIELD).cpu().numpy()
+    spec.t_peak = 0.02
+    osh = _oracle_shot(name, lev, L, dtl, op, ng, spec)
+    tr_ref = osh.forward(keep=False)
+    assert rel(q, osh.S_final) < 1e-5
+    assert rel(tr, tr_ref) < 1e-5
+
+
+@pytest.mark.parametrize("cond", [COND_CHARACTERISTIC, COND_PRESSURE])
+@pytest.mark.parametrize("ckpt", [0, 3])
+def test_rtm_image_parity(cond, ckpt):
+    from paper_1506_00907_amd import dgrtm
+    name = "two_layer_small:6:6:4:2"
+    lm, mm, rho, c, N = lib_mesh(name, BC_TRANSPARENT, 3)
+    m, op, lev, L, dtl = case(name, bc=BC_TRANSPARENT, n_levels=3)
+    spec = I.rtm_shot(n_rec=4)
+    spec.t_peak = 0.03
+    ng = 30
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=ng * dtl * 2 ** (L - 1), src=spec.src, f_peak=spec.f_peak,
+                                         t_peak=spec.t_peak, rec=spec.rec, ckpt_interval=ckpt))
+    tr = shot.forward()
+    shot.adjoint(tr, condition=cond, up=(0.0, 0.0, 1.0), g_image_start=4)
+    img = shot.image().cpu().numpy()
+    osh = _oracle_shot(name, lev, L, dtl, op, ng, spec)
+    tr_ref = osh.forward(condition=cond)
+    assert rel(tr.cpu().numpy(), tr_ref) < 1e-5
+    img_ref = osh.adjoint(tr.cpu().numpy().astype(np.float64), condition=cond, g_image_start=4)
+    assert rel(img, img_ref) < 1e-4
+
+
+def test_residual_fp64():
+    from paper_1506_00907_amd import dgrtm
+    lm, *_ = lib_mesh("two_layer_small:2:2:2:1", BC_TRANSPARENT, 1)
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=lm.dt_local))
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(100003).astype(np.float32)
+    b = rng.standard_normal(100003).astype(np.float32)
+    r = shot.residual(dev(a), dev(b))
+    ref = np.sum((a.astype(np.float64) - b.astype(np.float64)) ** 2)
+    assert abs(r - ref) < 1e-12 * ref
