@@ -1,0 +1,209 @@
+"""Benchmark: one RTM shot per step on one MI355X, FP32 path.
+
+A step is one pass of the whole hot path over one shot: forward source run from rest
+(multi-rate AB3, source checkpoints in HBM, receiver recording), then the backward pass
+(segment-wise recompute of the source wavefield from the checkpoints, backward receiver run
+with the recorded traces re-injected, characteristic imaging condition accumulated in FP64),
+then the image export.  Inputs (mesh, model, shot geometry) are seeded synthetic stand-ins
+for the paper's workloads and are resident in HBM before the timed region starts.
+
+Workload "rtm_200k": 2 x 2 x 1 km box, dipping two-layer model 1.5 / 3.0 km/s, 201 600
+jittered tetrahedra refined 2x at the interface, N = 4, 3 levels, 15 Hz Ricker source 8 m
+deep, 100 x 100 receivers 10 m deep, transparent boundaries, t_final = 1 s.
+
+Prints one JSON line (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def bytes_per_element_step(Np: int, Nfp: int, mode: int) -> int:
+    """Algorithmic HBM bytes of one element-step of the fused step kernel (FP32 state).
+
+    plain: q read + write (8 Np), rhs ring 2 reads + 1 write (12 Np), neighbour traces in and
+    own traces out (2 x 2 x 4 Nfp), geometry/material (20), neighbour ids and codes (8), flags (1).
+    record: + q-_S and r-_S written (2 Np).  image: + q-_S and 3 r-_S read (4 Np) and the FP64
+    image read and written (4 Np in float units).
+    """
+    words = 20 * Np + 16 * Nfp + 29
+    if mode == 1:
+        words += 2 * Np
+    if mode == 2:
+        words += 8 * Np
+    return 4 * words
+
+
+def flops_per_element_step(Np: int, Nfp: int) -> int:
+    # volume 6 Np^2 MACs, surface 2 x 4 Nfp Np MACs (LIFT on the p and the scalar v penalty)
+    return 2 * (6 * Np * Np + 8 * Nfp * Np)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1506_00907_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, mode_name: str):
+    """HBM bytes per launch from committed rocprofv3 PMC runs, if taken on the current kernel."""
+    p = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("modes", {}).get(mode_name)
+
+
+def cpu_baseline(mesh_in, rho, c, N, n_levels, seconds_target=15.0):
+    """The FP64 oracle's multi-rate forward stepping on the same mesh, a bounded sample of steps."""
+    import numpy as np
+
+    from oracle.dg import Operator
+    from oracle.mesh import BC_TRANSPARENT, OMesh, local_dt, lts_levels
+    from oracle.refelem import get_ref
+    from oracle.timestep import MRAB
+
+    om = OMesh(get_ref(N), mesh_in.verts, mesh_in.etov, bc_default=BC_TRANSPARENT)
+    op = Operator(om, rho, c)
+    lev, L, dtl = lts_levels(local_dt(om.verts, om.etov, c, N), om.EToE, n_levels)
+    rng = np.random.default_rng(0)
+    st = MRAB(op, lev, L, dtl)
+    st.set_state(rng.standard_normal((om.K, 4, op.ref.Np)) * 1e-3)
+    stride = 2 ** (L - lev)
+    t0 = time.perf_counter()
+    esteps = 0
+    while time.perf_counter() - t0 < seconds_target:
+        n = st.n
+        esteps += int(np.count_nonzero(n % stride == 0))
+        st.local_step()
+    dt = time.perf_counter() - t0
+    return {"value": esteps * 4 * op.ref.Np / dt / 1e9, "unit": "GDOF-steps/s", "cores": _threads(),
+            "kind": "oracle",
+            "sample": f"{st.n} local steps ({esteps} element-steps) of the FP64 multi-rate forward run "
+                      f"on the same {om.K}-element mesh, {dt:.1f} s"}
+
+
+def _threads() -> int:
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        if os.environ.get(k):
+            return int(os.environ[k])
+    return os.cpu_count() or 1
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rtm_200k")
+    ap.add_argument("--t-final", type=float, default=1.0)
+    ap.add_argument("--sample-every", type=int, default=7, help="time every n-th step-kernel launch")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the whole mesh and shot live on one MI355X "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1506_00907_amd import dgrtm, inputs as I
+
+    mm, rho, c, N = I.config_mesh(args.workload)
+    n_levels = 3
+    mesh = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, n_levels).bind("cuda")
+    spec = I.rtm_shot(box=mm.box, t_final=args.t_final)
+    shot = dgrtm.Shot(mesh, dgrtm.ShotSpec(t_final=spec.t_final, src=spec.src, f_peak=spec.f_peak,
+                                           t_peak=spec.t_peak, rec=spec.rec))
+    lev = mesh.export_setup()["level"].astype(np.int64)
+    L = mesh.L
+    hist = np.bincount(lev, minlength=L + 1)[1:]
+    esteps_global = int(sum(hist[l - 1] * 2 ** (l - 1) for l in range(1, L + 1)))
+    ng = shot.n_global
+    dof = 4 * mesh.Np
+    traces = torch.empty((shot.n_rec, ng + 1), dtype=torch.float32, device="cuda")
+    img = torch.zeros((mesh.K, mesh.Np), dtype=torch.float64, device="cuda")
+
+    def one_shot():
+        shot.forward(traces)
+        shot.adjoint(traces, condition=dgrtm.IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start=0)
+        shot.image(img)
+
+    for _ in range(args.warmup):
+        one_shot()
+    torch.cuda.synchronize()
+    shot.profile_start(args.sample_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = []
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        one_shot()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = {m: shot.profile_read(m) for m in (0, 1, 2)}
+    # element-steps per shot: forward + recompute + backward, each over every global step
+    es_shot = 3 * ng * esteps_global
+    value = es_shot * args.steps * dof / wall / 1e9
+    sr_equiv = 3 * ng * mesh.K * 2 ** (L - 1) * args.steps * dof / wall / 1e9
+    mode_names = {0: "forward_step", 1: "recompute_step", 2: "image_step"}
+    rl = {}
+    for m, p in prof.items():
+        if p["launches"] == 0:
+            continue
+        b = p["element_steps"] * bytes_per_element_step(mesh.Np, mesh.Nfp, m)
+        rl[mode_names[m]] = {"avg_launch_us": 1e3 * p["kernel_ms"] / p["launches"],
+                             "achieved_GBs": b / (p["kernel_ms"] * 1e-3) / 1e9,
+                             "kernel_ms_sampled": p["kernel_ms"], "launches_sampled": p["launches"],
+                             "algo_bytes_per_launch": b / p["launches"]}
+    dom = max(rl, key=lambda k: prof[{v: k2 for k2, v in mode_names.items()}[k]]["kernel_ms"])
+    tr = load_traffic(args.workload, dom)
+    out = {
+        "metric": "GDOF-steps/s FP32 vs split-BF16 at stated error; shots/h + p50/p99 shot latency",
+        "value": round(value, 3),
+        "unit": "GDOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic (seeded mesh, model and shot; no dataset)",
+        "config": {"workload": args.workload, "elements": int(mesh.K), "order_N": int(N), "levels": int(L),
+                   "level_histogram_coarse_to_fine": [int(x) for x in hist], "global_steps": int(ng),
+                   "t_final_s": round(ng * mesh.dt_local * 2 ** (L - 1), 6), "receivers": int(shot.n_rec),
+                   "image": "characteristic", "parallelism": "single GPU"},
+        "images_per_hour": round(3600.0 * args.steps / wall, 2),
+        "shot_latency_s": {"p50": round(float(np.percentile(lat, 50)), 3),
+                           "p99": round(float(np.percentile(lat, 99)), 3)},
+        "single_rate_equivalent_GDOF_steps_s": round(sr_equiv, 3),
+        "roofline": {"bound": "hbm", "kernel": f"step_kernel ({dom})",
+                     "achieved": round(rl[dom]["achieved_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(rl[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                     "traffic": tr, "per_mode": rl},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mm, rho, c, N, n_levels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -197,6 +197,20 @@ dgrtm_status dgrtm_get_state(dgrtm_shot shot, int which, float *q);
  * with the shot's source when with_source != 0 and the wavefield is the source field. */
 dgrtm_status dgrtm_run(dgrtm_shot shot, int which, int64_t n_global, int reversed, int with_source);
 
+/* ---- measurement ---- */
+
+/* Time every sample_every-th launch of the fused step kernel with a pair of HIP events on the
+ * bound stream (0 = off); clears earlier samples.  The events are created on the host by the
+ * library and released by dgrtm_shot_destroy. */
+dgrtm_status dgrtm_profile_start(dgrtm_shot shot, int sample_every);
+
+/* Sum over the sampled launches of step-kernel mode `mode` (0 plain forward step, 1 source
+ * recompute with segment recording, 2 backward step with imaging, 3 rhs only): total kernel
+ * time in milliseconds, number of sampled launches, and real elements updated by them.
+ * Synchronises the stream. */
+dgrtm_status dgrtm_profile_read(dgrtm_shot shot, int mode, double *kernel_ms, int64_t *launches,
+                                int64_t *element_steps);
+
 void dgrtm_shot_destroy(dgrtm_shot shot);
 
 #ifdef __cplusplus

@@ -87,6 +87,19 @@ struct dgrtm_shot_s {
   float *traces = nullptr;     // n_rec x (n_global + 1)
   double *red = nullptr;       // FP64 reduction scratch
   bool forward_done = false;
+  // sampled HIP-event timing of the step kernel (dgrtm_profile_*)
+  int prof_every = 0;
+  int64_t prof_counter = 0;
+  std::vector<hipEvent_t> prof_ev;
+  struct ProfRec {
+    int mode;
+    int64_t elems;
+    size_t ev;
+  };
+  std::vector<ProfRec> prof_rec;
+  ~dgrtm_shot_s() {
+    for (auto e : prof_ev) (void)hipEventDestroy(e);
+  }
 };
 
 static int64_t level_end_h(const HostMesh &m, int l) { return l == 1 ? m.lev_begin[m.L] : m.lev_begin[l - 2]; }
@@ -548,13 +561,68 @@ static dgrtm_status zero_field(dgrtm_shot sh, Field &f) {
   return DGRTM_OK;
 }
 
+static int step_mode(const StepArgs &a) {
+  return a.rhs_out ? MODE_RHS_ONLY : a.img ? MODE_IMAGE : a.seg_q ? MODE_RECORD_SEG : MODE_PLAIN;
+}
+
+// real elements in the active prefix [0, k_end)
+static int64_t active_elements(const HostMesh &h, int64_t k_end) {
+  int64_t n = 0;
+  for (int l = 1; l <= h.L; ++l)
+    if (h.lev_begin[l - 1] < k_end) n += h.lev_count[l - 1];
+  return n;
+}
+
 // one local step of a field: a is prepared by the caller except tau / k_end
 static dgrtm_status local_step(dgrtm_shot sh, Field &f, StepArgs &a) {
   dgrtm_mesh m = sh->mesh;
   a.tau = f.tau;
   a.k_end = active_end(m->hm, f.tau);
+  const bool prof = sh->prof_every > 0 && (sh->prof_counter++ % sh->prof_every) == 0;
+  size_t ev = 0;
+  if (prof) {
+    ev = sh->prof_rec.size() * 2;
+    while (sh->prof_ev.size() < ev + 2) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      sh->prof_ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(sh->prof_ev[ev], m->stream));
+  }
   HIPCHK(launch_step(m->ref.N, a, m->stream));
+  if (prof) {
+    HIPCHK(hipEventRecord(sh->prof_ev[ev + 1], m->stream));
+    sh->prof_rec.push_back({step_mode(a), active_elements(m->hm, a.k_end), ev});
+  }
   f.tau += 1;
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_profile_start(dgrtm_shot sh, int sample_every) {
+  if (!sh || sample_every < 0) return fail(DGRTM_ERR_ARG, "dgrtm_profile_start: bad argument");
+  sh->prof_every = sample_every;
+  sh->prof_counter = 0;
+  sh->prof_rec.clear();
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_profile_read(dgrtm_shot sh, int mode, double *kernel_ms, int64_t *launches,
+                                           int64_t *element_steps) {
+  if (!sh || mode < 0 || mode > 3) return fail(DGRTM_ERR_ARG, "dgrtm_profile_read: bad argument");
+  HIPCHK(hipStreamSynchronize(sh->mesh->stream));
+  double ms = 0.0;
+  int64_t n = 0, es = 0;
+  for (const auto &r : sh->prof_rec) {
+    if (r.mode != mode) continue;
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, sh->prof_ev[r.ev], sh->prof_ev[r.ev + 1]));
+    ms += t;
+    ++n;
+    es += r.elems;
+  }
+  if (kernel_ms) *kernel_ms = ms;
+  if (launches) *launches = n;
+  if (element_steps) *element_steps = es;
   return DGRTM_OK;
 }
 

@@ -43,6 +43,9 @@ _SYMBOLS = {
     "dgrtm_set_state": (C.c_int32, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dgrtm_get_state": (C.c_int32, [C.c_void_p, C.c_int, C.c_void_p]),
     "dgrtm_run": (C.c_int32, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_int]),
+    "dgrtm_profile_start": (C.c_int32, [C.c_void_p, C.c_int]),
+    "dgrtm_profile_read": (C.c_int32, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64)]),
     "dgrtm_shot_destroy": (None, [C.c_void_p]),
 }
 
@@ -256,6 +259,16 @@ class Shot:
 
     def run(self, which: int, n_global: int, reversed_time: bool = False, with_source: bool = False):
         _check(_lib.dgrtm_run(self.h, int(which), int(n_global), int(reversed_time), int(with_source)), "dgrtm_run")
+
+    # ---- measurement
+    def profile_start(self, sample_every: int):
+        _check(_lib.dgrtm_profile_start(self.h, int(sample_every)), "dgrtm_profile_start")
+
+    def profile_read(self, mode: int):
+        ms, n, es = C.c_double(), C.c_int64(), C.c_int64()
+        _check(_lib.dgrtm_profile_read(self.h, int(mode), C.byref(ms), C.byref(n), C.byref(es)),
+               "dgrtm_profile_read")
+        return {"kernel_ms": ms.value, "launches": n.value, "element_steps": es.value}
 
     def __del__(self):
         if getattr(self, "h", None):
