@@ -58,6 +58,12 @@ typedef int32_t dgrtm_status;
 #define DGRTM_IMAGE_PRESSURE 0
 #define DGRTM_IMAGE_CHARACTERISTIC 1
 
+/* arithmetic of the element operator products: FP32 MFMA, or split-BF16 MFMA (A x evaluated as
+ * A_hi x_hi + A_hi x_lo + A_lo x_hi with A = A_hi + A_lo, x = x_hi + x_lo in bf16, FP32 accumulation).
+ * State, update and traces are FP32 in both; the image is accumulated in FP64 in both. */
+#define DGRTM_FP32 0
+#define DGRTM_SPLIT_BF16 1
+
 /* which wavefield of a shot a test hook addresses */
 #define DGRTM_SOURCE_FIELD 0
 #define DGRTM_RECEIVER_FIELD 1
@@ -138,6 +144,8 @@ typedef struct dgrtm_shot_args {
   const double *rec_xyz;   /* host, n_rec x 3 */
   double t_final;          /* rounded up to a whole number of global steps */
   int64_t ckpt_interval;   /* global steps between source checkpoints; 0 = chosen to minimise memory */
+  int32_t precision;       /* DGRTM_FP32 or DGRTM_SPLIT_BF16 */
+  int32_t reserved;
 } dgrtm_shot_args;
 
 /* Number of global steps of a shot and local steps per global step. */

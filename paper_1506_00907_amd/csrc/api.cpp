@@ -51,10 +51,11 @@ struct dgrtm_mesh_s {
   float *geo = nullptr;
   int *nbr = nullptr, *ncode = nullptr, *eflag = nullptr;
   float *ops = nullptr;
+  uint32_t *ops_bf16 = nullptr;
   int8_t *nbr_index = nullptr;
   int64_t *s2u = nullptr;
   std::vector<int> h_eflag;  // base flags (valid, has finer neighbour)
-  int64_t n_ops = 0;
+  int64_t n_ops = 0, n_ops_bf16 = 0;
 };
 
 struct PointSet {
@@ -145,6 +146,8 @@ static size_t mesh_layout(dgrtm_mesh m, Bump &b) {
   int *ncode = b.take<int>((size_t)4 * K);
   int *eflag = b.take<int>((size_t)K);
   float *ops = b.take<float>((size_t)n_ops);
+  const int64_t n_ops_bf16 = op_fragment_bf16_words(m->ref.N);
+  uint32_t *ops_bf16 = b.take<uint32_t>((size_t)n_ops_bf16);
   int8_t *nidx = b.take<int8_t>((size_t)4 * 4 * 6 * m->ref.Nfp);
   int64_t *s2u = b.take<int64_t>((size_t)K);
   if (b.base) {  // a sizing pass (no base) leaves the handle untouched
@@ -154,6 +157,8 @@ static size_t mesh_layout(dgrtm_mesh m, Bump &b) {
     m->eflag = eflag;
     m->n_ops = n_ops;
     m->ops = ops;
+    m->n_ops_bf16 = n_ops_bf16;
+    m->ops_bf16 = ops_bf16;
     m->nbr_index = nidx;
     m->s2u = s2u;
   }
@@ -230,6 +235,8 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
   for (int i = 0; i < Np * F; ++i) L[i] = (float)R.LIFT[i];
   std::vector<float> frag(m->n_ops);
   build_op_fragments(R.N, Dr.data(), Ds.data(), Dt.data(), L.data(), frag.data());
+  std::vector<uint32_t> fragb(m->n_ops_bf16);
+  build_op_fragments_bf16(R.N, R.Dr.data(), R.Ds.data(), R.Dt.data(), R.LIFT.data(), fragb.data());
   std::vector<int8_t> nidx(R.nbr_index.size());
   for (size_t i = 0; i < nidx.size(); ++i) nidx[i] = (int8_t)R.nbr_index[i];
   hipStream_t st = m->stream;
@@ -238,6 +245,7 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
   HIPCHK(hipMemcpyAsync(m->ncode, ncode.data(), ncode.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(m->eflag, m->h_eflag.data(), K * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(m->ops, frag.data(), frag.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(m->ops_bf16, fragb.data(), fragb.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(m->nbr_index, nidx.data(), nidx.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(m->s2u, h.sorted_to_user.data(), K * 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -301,6 +309,7 @@ static dgrtm_status check_args(dgrtm_mesh m, const dgrtm_shot_args *a) {
   if (!(a->t_final > 0)) return fail(DGRTM_ERR_ARG, "t_final must be positive");
   if (a->n_rec < 0 || (a->n_rec > 0 && !a->rec_xyz)) return fail(DGRTM_ERR_ARG, "bad receivers");
   if (a->ckpt_interval < 0) return fail(DGRTM_ERR_ARG, "bad ckpt_interval");
+  if (a->precision != DGRTM_FP32 && a->precision != DGRTM_SPLIT_BF16) return fail(DGRTM_ERR_ARG, "bad precision");
   return DGRTM_OK;
 }
 
@@ -512,6 +521,8 @@ static StepArgs base_args(dgrtm_shot sh, Field &f, bool reversed) {
   a.ncode = m->ncode;
   a.eflag = m->eflag;
   a.ops = m->ops;
+  a.ops_bf16 = m->ops_bf16;
+  a.precision = sh->args.precision;
   a.nbr_index = m->nbr_index;
   a.Ktot = h.Ktot;
   a.L = h.L;

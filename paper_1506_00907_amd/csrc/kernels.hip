@@ -9,6 +9,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <cstring>
 
 namespace dgrtm {
 
@@ -82,10 +83,268 @@ __device__ __forceinline__ int64_t level_end(const int64_t *lev_begin, int L, in
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
 
 // select one of four compile-time constants by the lane group g = lane / 16
 __device__ __forceinline__ int sel4(int g, int a, int b, int c, int d) {
   return g == 0 ? a : (g == 1 ? b : (g == 2 ? c : d));
+}
+
+// round-to-nearest-even bf16 of x (upper 16 bits of the FP32 pattern)
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+
+// x = hi + lo + O(2^-17 |x|), hi and lo bf16
+__device__ __forceinline__ void split_bf16(float x, short &hi, short &lo) {
+  const uint32_t h = bf16_bits(x);
+  hi = (short)h;
+  lo = (short)bf16_bits(x - __uint_as_float(h << 16));
+}
+
+// Geometry of face f of the lane's element and where its neighbour's traces live.
+struct FaceCtx {
+  float nx, ny, nz, Fs, taup, tauv;
+  int nb, f2;
+  const float *trp;
+  const int8_t *tab;
+};
+
+template <int N>
+__device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, int f, int64_t k, const float *gg) {
+  constexpr int Nfp = Dims<N>::Nfp, F = Dims<N>::F;
+  const int64_t K = a.Ktot;
+  FaceCtx c;
+  float nx, ny, nz;
+  if (f == 0) { nx = -gg[6]; ny = -gg[7]; nz = -gg[8]; }
+  else if (f == 1) { nx = -gg[3]; ny = -gg[4]; nz = -gg[5]; }
+  else if (f == 2) { nx = gg[0] + gg[3] + gg[6]; ny = gg[1] + gg[4] + gg[7]; nz = gg[2] + gg[5] + gg[8]; }
+  else { nx = -gg[0]; ny = -gg[1]; nz = -gg[2]; }
+  c.Fs = sqrtf(nx * nx + ny * ny + nz * nz);  // J_f / J
+  const float inv = 1.0f / c.Fs;
+  c.nx = nx * inv; c.ny = ny * inv; c.nz = nz * inv;
+  c.nb = a.nbr[f * K + k];
+  const int code = a.ncode[f * K + k];
+  c.taup = a.tau_sign * gg[12 + f];
+  c.tauv = a.tau_sign * gg[16 + f];
+  c.trp = a.tr;
+  c.tab = a.nbr_index;
+  c.f2 = 0;
+  if (c.nb >= 0) {
+    c.f2 = code & 3;
+    const int perm = (code >> 2) & 7;
+    const int shn = a.L - (code >> 5);
+    // neighbour on its own step grid -> parity slot, otherwise (one level coarser) its mid step
+    const int slot = ((a.tau & ((1LL << shn) - 1)) == 0) ? (int)((a.tau >> shn) & 1) : 2;
+    c.trp = a.tr + (int64_t)slot * 2 * F * K;
+    c.tab = a.nbr_index + ((f * 4 + c.f2) * 6 + perm) * Nfp;
+  }
+  return c;
+}
+
+// Penalty terms at face node s (volume node `node`) of the lane's element, already scaled by
+// J_f/J: returns -P^p and the scalar part of P^v (P^{v_i} = n_i * Pv).
+template <int N>
+__device__ __forceinline__ void penalty(const StepArgs &a, const FaceCtx &c, int s, int node, int64_t k, float rc2,
+                                        float irho, float &mPp, float &Pv) {
+  constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F;
+  const int64_t K = a.Ktot;
+  const float pm = a.q[(int64_t)node * K + k];
+  const float nvm = c.nx * a.q[(int64_t)(Np + node) * K + k] + c.ny * a.q[(int64_t)(2 * Np + node) * K + k] +
+                    c.nz * a.q[(int64_t)(3 * Np + node) * K + k];
+  float pp, nvp;
+  if (c.nb >= 0) {
+    const int64_t row = c.f2 * Nfp + c.tab[s];
+    pp = c.trp[row * K + c.nb];
+    nvp = -c.trp[(F + row) * K + c.nb];  // n- . v+ = -(n+ . v+)
+  } else if (c.nb == -1) {  // rigid wall
+    pp = pm;
+    nvp = -nvm;
+  } else if (c.nb == -2) {  // transparent
+    pp = 0.0f;
+    nvp = 0.0f;
+  } else {  // free surface
+    pp = -pm;
+    nvp = nvm;
+  }
+  const float dp = pp - pm, dnv = nvp - nvm;
+  mPp = -0.5f * rc2 * (dnv - c.taup * dp) * c.Fs;
+  Pv = 0.5f * irho * (dp - c.tauv * dnv) * c.Fs;
+}
+
+// Everything after the operator products, in the MFMA C layout (lane: element e, rows
+// 16 rt + 4 g + i): point sources, output of a bare rhs, AB3 update, rhs ring, traces of the new
+// state and of the half step, source-wavefield segment record and FP64 image accumulation.
+template <int N, int MODE>
+__device__ __forceinline__ void tile_tail(const StepArgs &a, int64_t k, int g, int lev, int sh, int64_t m, int flag,
+                                          float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
+                                          v4f (&rp)[Dims<N>::NR], v4f (&rvx)[Dims<N>::NR], v4f (&rvy)[Dims<N>::NR],
+                                          v4f (&rvz)[Dims<N>::NR]) {
+  constexpr Tab<N> T{};
+  constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F, NR = Dims<N>::NR;
+  const int64_t K = a.Ktot;
+  const bool valid = (flag & 1) != 0;
+  if (a.out_sign < 0.0f) {
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt) {
+      rp[rt] = -rp[rt]; rvx[rt] = -rvx[rt]; rvy[rt] = -rvy[rt]; rvz[rt] = -rvz[rt];
+    }
+  }
+  // ---- point sources (projected delta into the pressure equation)
+  if (valid && (flag & 4)) {
+    const int s0 = a.src_start[k], scn = a.src_count[k];
+    for (int en = s0; en < s0 + scn; ++en) {
+      const int pt = a.src_point[en];
+      float amp = 0.0f;
+      if (a.amp_mode == 0) {
+        amp = a.wavelet[a.tau];
+      } else {
+        const int64_t j = a.data_j;
+        const int64_t gq = j / a.n_local, rem = j % a.n_local;
+        if (j >= 0 && (gq < a.n_t - 1 || (gq == a.n_t - 1 && rem == 0))) {
+          const float *d = a.data + (int64_t)pt * a.n_t;
+          if (rem == 0) amp = d[gq];
+          else {
+            const float th = (float)rem / (float)a.n_local;
+            amp = (1.0f - th) * d[gq] + th * d[gq + 1];
+          }
+        }
+      }
+      amp *= a.src_scale;
+      const float *w = a.src_w + (int64_t)pt * Np;
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int n = 16 * rt + 4 * g + i;
+          if (16 * rt + 15 < Np || n < Np) rp[rt][i] += amp * w[n];
+        }
+    }
+  }
+  if (!valid) return;
+  if constexpr (MODE == MODE_RHS_ONLY) {
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = 16 * rt + 4 * g + i;
+        if (16 * rt + 15 < Np || n < Np) {
+          a.rhs_out[(int64_t)(0 * Np + n) * K + k] = rp[rt][i];
+          a.rhs_out[(int64_t)(1 * Np + n) * K + k] = rvx[rt][i];
+          a.rhs_out[(int64_t)(2 * Np + n) * K + k] = rvy[rt][i];
+          a.rhs_out[(int64_t)(3 * Np + n) * K + k] = rvz[rt][i];
+        }
+      }
+    return;
+  }
+  const int64_t slab = (int64_t)4 * Np * K;
+  const float dtl = (float)(a.dt_local * (double)(1LL << sh));
+  float *__restrict__ R0 = a.ring + (m % 3) * slab;
+  const float *__restrict__ R1 = a.ring + ((m + 2) % 3) * slab;
+  const float *__restrict__ R2 = a.ring + ((m + 1) % 3) * slab;
+  float *__restrict__ trw = a.tr + ((m + 1) & 1) * (int64_t)2 * F * K;
+  float *__restrict__ trm = a.tr + (int64_t)2 * 2 * F * K;
+  const bool mid = (flag & 2) != 0;
+  float *q = a.q;
+  const float ux = a.up[0], uy = a.up[1], uz = a.up[2];
+  const float zs = a.condition ? Z : 0.0f;
+  int64_t kk = 0, Pl = 0, jS = 0;
+  bool do_img = false;
+  if constexpr (MODE == MODE_RECORD_SEG || MODE == MODE_IMAGE) {
+    kk = k - a.lev_begin[lev - 1];
+    Pl = level_end(a.lev_begin, a.L, lev) - a.lev_begin[lev - 1];
+  }
+  if constexpr (MODE == MODE_RECORD_SEG) jS = m - a.seg_m0[lev - 1];
+  if constexpr (MODE == MODE_IMAGE) {
+    const int64_t mS = a.own_total[lev - 1] - m - 1;  // source step [t_a, t_b] of this receiver step
+    jS = mS - a.seg_m0[lev - 1];
+    do_img = (mS << sh) >= a.image_from && jS >= 0 && jS < a.seg_len[lev - 1];
+  }
+  const double dtd = a.dt_local * (double)(1LL << sh);
+
+#pragma unroll
+  for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int n = 16 * rt + 4 * g + i;
+      if (!(16 * rt + 15 < Np || n < Np)) continue;
+      const float r[4] = {rp[rt][i], rvx[rt][i], rvy[rt][i], rvz[rt][i]};
+      float qo[4], h1[4], h2[4], qn[4], qm[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t idx = (int64_t)(c * Np + n) * K + k;
+        h1[c] = R1[idx];
+        h2[c] = R2[idx];
+        qo[c] = q[idx];
+        R0[idx] = r[c];
+        qn[c] = qo[c] + dtl * (kA0 * r[c] + kA1 * h1[c] + kA2 * h2[c]);
+        q[idx] = qn[c];
+        qm[c] = qo[c] + dtl * (kB0 * r[c] + kB1 * h1[c] + kB2 * h2[c]);
+      }
+      if constexpr (MODE == MODE_RECORD_SEG) {
+        const float qminus = qo[0] - zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
+        const float rminus = r[0] - zs * (ux * r[1] + uy * r[2] + uz * r[3]);
+        a.seg_q[a.seg_q_off[lev - 1] + (jS * Np + n) * Pl + kk] = qminus;
+        a.seg_r[a.seg_r_off[lev - 1] + ((jS + 2) * Np + n) * Pl + kk] = rminus;
+      }
+      if constexpr (MODE == MODE_IMAGE) {
+        if (do_img) {
+          const float *sq = a.seg_q + a.seg_q_off[lev - 1];
+          const float *sr = a.seg_r + a.seg_r_off[lev - 1];
+          const double qS = sq[(jS * Np + n) * Pl + kk];
+          const double rS[3] = {sr[((jS + 2) * Np + n) * Pl + kk], sr[((jS + 1) * Np + n) * Pl + kk],
+                                sr[(jS * Np + n) * Pl + kk]};
+          const double qR = qo[0] + zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
+          const double rR[3] = {r[0] + zs * (ux * r[1] + uy * r[2] + uz * r[3]),
+                                h1[0] + zs * (ux * h1[1] + uy * h1[2] + uz * h1[3]),
+                                h2[0] + zs * (ux * h2[1] + uy * h2[2] + uz * h2[3])};
+          double inc2 = 0.0, inc3 = 0.0;
+#pragma unroll
+          for (int s = 0; s < 3; ++s) inc2 += kE[s] * (qS * rR[s] + rS[s] * qR);
+#pragma unroll
+          for (int s1 = 0; s1 < 3; ++s1)
+#pragma unroll
+            for (int s2 = 0; s2 < 3; ++s2) inc3 += kCm[s1][s2] * rS[s1] * rR[s2];
+          a.img[(int64_t)n * K + k] += dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const int fi = sel4(g, T.fidx[min(16 * rt + i, Np - 1)][f], T.fidx[min(16 * rt + 4 + i, Np - 1)][f],
+                            T.fidx[min(16 * rt + 8 + i, Np - 1)][f], T.fidx[min(16 * rt + 12 + i, Np - 1)][f]);
+        if (fi >= 0) {
+          const int64_t r0 = (int64_t)(f * Nfp + fi) * K + k;
+          const int64_t r1 = (int64_t)(F + f * Nfp + fi) * K + k;
+          trw[r0] = qn[0];
+          trw[r1] = nfx[f] * qn[1] + nfy[f] * qn[2] + nfz[f] * qn[3];
+          if (mid) {
+            trm[r0] = qm[0];
+            trm[r1] = nfx[f] * qm[1] + nfy[f] * qm[2] + nfz[f] * qm[3];
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// converts the volume accumulators (sum_j D_j U_j and D_j p) into the pressure and velocity rhs
+template <int NR>
+__device__ __forceinline__ void volume_to_rhs(const float *gg, const v4f (&cp)[NR], const v4f (&w0)[NR],
+                                              const v4f (&w1)[NR], const v4f (&w2)[NR], v4f (&rp)[NR],
+                                              v4f (&rvx)[NR], v4f (&rvy)[NR], v4f (&rvz)[NR]) {
+  const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
+              tz = gg[8], rc2 = gg[9], irho = gg[10];
+#pragma unroll
+  for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float wr = w0[rt][i], ws = w1[rt][i], wt = w2[rt][i];
+      rp[rt][i] = -rc2 * cp[rt][i];
+      rvx[rt][i] = -irho * (rx * wr + sx * ws + tx * wt);
+      rvy[rt][i] = -irho * (ry * wr + sy * ws + ty * wt);
+      rvz[rt][i] = -irho * (rz * wr + sz * ws + tz * wt);
+    }
 }
 
 // One wavefront owns a tile of 16 consecutive elements.  The element-batched operator products
@@ -98,7 +357,7 @@ template <int N, int MODE, bool OPS_LDS>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
   constexpr Tab<N> T{};
   using Dm = Dims<N>;
-  constexpr int Np = Dm::Np, Nfp = Dm::Nfp, F = Dm::F, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
+  constexpr int Np = Dm::Np, Nfp = Dm::Nfp, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
   extern __shared__ float sops[];
   const float *ops = a.ops;
   if constexpr (OPS_LDS) {
@@ -110,7 +369,6 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
   const int e = lane & 15, g = lane >> 4;
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
-  const int64_t slab = (int64_t)4 * Np * K;
 
   for (int64_t grp = blockIdx.x; grp * 4 < ntiles; grp += gridDim.x) {
     const int64_t tile = grp * 4 + wave;
@@ -123,7 +381,6 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
     const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
     const float *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;    // [NR][4*FC][64]
     const int flag = a.eflag[k];
-    const bool valid = (flag & 1) != 0;
     const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
     const int sh = a.L - lev;
     const int64_t m = a.tau >> sh;
@@ -133,11 +390,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
     for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[i * K + k];
     const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
                 tz = gg[8];
-    const float rc2 = gg[9], irho = gg[10], Z = gg[11];
-    const float *__restrict__ q0 = a.q;
-    const float *__restrict__ q1 = a.q + (int64_t)Np * K;
-    const float *__restrict__ q2 = a.q + (int64_t)2 * Np * K;
-    const float *__restrict__ q3 = a.q + (int64_t)3 * Np * K;
+    const float rc2 = gg[9], irho = gg[10];
 
     // ---- volume: Cp = sum_j D_j U_j and W_j = D_j p
     v4f cp[NR], w0[NR], w1[NR], w2[NR];
@@ -148,7 +401,10 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
       const int mm = 4 * c + g;
       float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
       if (mm < Np) {
-        p = q0[mm * K + k]; vx = q1[mm * K + k]; vy = q2[mm * K + k]; vz = q3[mm * K + k];
+        p = a.q[(int64_t)mm * K + k];
+        vx = a.q[(int64_t)(Np + mm) * K + k];
+        vy = a.q[(int64_t)(2 * Np + mm) * K + k];
+        vz = a.q[(int64_t)(3 * Np + mm) * K + k];
       }
       const float Ur = rx * vx + ry * vy + rz * vz;
       const float Us = sx * vx + sy * vy + sz * vz;
@@ -167,79 +423,30 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
       }
     }
     v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
-#pragma unroll
-    for (int rt = 0; rt < NR; ++rt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float wr = w0[rt][i], ws = w1[rt][i], wt = w2[rt][i];
-        rp[rt][i] = -rc2 * cp[rt][i];
-        rvx[rt][i] = -irho * (rx * wr + sx * ws + tx * wt);
-        rvy[rt][i] = -irho * (ry * wr + sy * ws + ty * wt);
-        rvz[rt][i] = -irho * (rz * wr + sz * ws + tz * wt);
-      }
+    volume_to_rhs<NR>(gg, cp, w0, w1, w2, rp, rvx, rvy, rvz);
 
     // ---- surface: rp -= LIFT Pp (accumulated by the MFMA with -Pp), G_f = LIFT_f Pv, rv -= n_f G_f
     float nfx[4], nfy[4], nfz[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      float nx, ny, nz;
-      if (f == 0) { nx = -tx; ny = -ty; nz = -tz; }
-      else if (f == 1) { nx = -sx; ny = -sy; nz = -sz; }
-      else if (f == 2) { nx = rx + sx + tx; ny = ry + sy + ty; nz = rz + sz + tz; }
-      else { nx = -rx; ny = -ry; nz = -rz; }
-      const float Fs = sqrtf(nx * nx + ny * ny + nz * nz);
-      const float inv = 1.0f / Fs;
-      nx *= inv; ny *= inv; nz *= inv;
-      nfx[f] = nx; nfy[f] = ny; nfz[f] = nz;
-      const int nb = a.nbr[f * K + k];
-      const int code = a.ncode[f * K + k];
-      const float taup = a.tau_sign * gg[12 + f], tauv = a.tau_sign * gg[16 + f];
-      const float *trp = a.tr;
-      const int8_t *tab = a.nbr_index;
-      int f2 = 0;
-      if (nb >= 0) {
-        f2 = code & 3;
-        const int perm = (code >> 2) & 7;
-        const int shn = a.L - (code >> 5);
-        const int slot = ((a.tau & ((1LL << shn) - 1)) == 0) ? (int)((a.tau >> shn) & 1) : 2;
-        trp = a.tr + (int64_t)slot * 2 * F * K;
-        tab = a.nbr_index + ((f * 4 + f2) * 6 + perm) * Nfp;
-      }
+      const FaceCtx fc = face_ctx<N>(a, f, k, gg);
+      nfx[f] = fc.nx; nfy[f] = fc.ny; nfz[f] = fc.nz;
       v4f G[NR];
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int cc = 0; cc < FC; ++cc) {
         const int s = 4 * cc + g;   // face node handled by this lane in this chunk
-        float Pp = 0.f, Pv = 0.f;
+        float mPp = 0.f, Pv = 0.f;
         if (4 * cc + 3 < Nfp || s < Nfp) {
           const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
                                 T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
-          const float pm = q0[node * K + k];
-          const float nvm = nx * q1[node * K + k] + ny * q2[node * K + k] + nz * q3[node * K + k];
-          float pp, nvp;
-          if (nb >= 0) {
-            const int64_t row = f2 * Nfp + tab[s];
-            pp = trp[row * K + nb];
-            nvp = -trp[(F + row) * K + nb];
-          } else if (nb == -1) {  // rigid wall
-            pp = pm;
-            nvp = -nvm;
-          } else if (nb == -2) {  // transparent
-            pp = 0.0f;
-            nvp = 0.0f;
-          } else {  // free surface
-            pp = -pm;
-            nvp = nvm;
-          }
-          const float dp = pp - pm, dnv = nvp - nvm;
-          Pp = -0.5f * rc2 * (dnv - taup * dp) * Fs;
-          Pv = 0.5f * irho * (dp - tauv * dnv) * Fs;
+          penalty<N>(a, fc, s, node, k, rc2, irho, mPp, Pv);
         }
 #pragma unroll
         for (int rt = 0; rt < NR; ++rt) {
           const float al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
-          rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pp, rp[rt], 0, 0, 0);
+          rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
           G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
         }
       }
@@ -247,158 +454,149 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
       for (int rt = 0; rt < NR; ++rt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          rvx[rt][i] -= nx * G[rt][i];
-          rvy[rt][i] -= ny * G[rt][i];
-          rvz[rt][i] -= nz * G[rt][i];
+          rvx[rt][i] -= fc.nx * G[rt][i];
+          rvy[rt][i] -= fc.ny * G[rt][i];
+          rvz[rt][i] -= fc.nz * G[rt][i];
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (a.out_sign < 0.0f) {
+    tile_tail<N, MODE>(a, k, g, lev, sh, m, flag, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+  }
+}
+
+// Split-BF16 form: every operator product A x is evaluated as A_hi x_hi + A_hi x_lo + A_lo x_hi
+// on v_mfma_f32_16x16x16_bf16 with FP32 accumulation (A = A_hi + A_lo and x = x_hi + x_lo in
+// bf16).  Lane l holds A[l%16][4(l/16)..4(l/16)+3] and B[4(l/16)..+3][l%16]; C as above.
+// Operator fragments: per (operator, row tile, 16-column chunk) 64 lanes x (4 hi + 4 lo) bf16.
+template <int N>
+struct DimsB {
+  static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, NR = Dims<N>::NR;
+  static constexpr int NK = (Np + 15) / 16;    // 16-column chunks of D_j
+  static constexpr int FC = (Nfp + 15) / 16;   // 16-column chunks per face of LIFT
+  static constexpr int FRAG = 3 * NR * NK + NR * 4 * FC;          // fragments
+  static constexpr int OPS_U4 = FRAG * 64;                        // uint4 per fragment lane
+};
+
+template <int N, int MODE, bool OPS_LDS>
+__global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
+  constexpr Tab<N> T{};
+  using Dm = DimsB<N>;
+  constexpr int Np = Dm::Np, Nfp = Dm::Nfp, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
+  extern __shared__ uint4 sopsb[];
+  const uint4 *ops = reinterpret_cast<const uint4 *>(a.ops_bf16);
+  if constexpr (OPS_LDS) {
+    for (int i = threadIdx.x; i < Dm::OPS_U4; i += blockDim.x) sopsb[i] = ops[i];
+    __syncthreads();
+    ops = sopsb;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = lane & 15, g = lane >> 4;
+  const int64_t K = a.Ktot;
+  const int64_t ntiles = a.k_end >> 4;
+  auto hi = [](const uint4 &u) { return __builtin_bit_cast(v4s, uint2{u.x, u.y}); };
+  auto lo = [](const uint4 &u) { return __builtin_bit_cast(v4s, uint2{u.z, u.w}); };
+
+  for (int64_t grp = blockIdx.x; grp * 4 < ntiles; grp += gridDim.x) {
+    const int64_t tile = grp * 4 + wave;
+    if (tile >= ntiles) continue;
+    const int64_t k = tile * 16 + e;
+    int opaque0;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
+    const uint4 *__restrict__ fD = ops + opaque0;                      // [3][NR][NK][64]
+    const uint4 *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;   // [NR][4*FC][64]
+    const int flag = a.eflag[k];
+    const int lev = level_of(a.lev_begin, a.L, tile * 16);
+    const int sh = a.L - lev;
+    const int64_t m = a.tau >> sh;
+    float gg[kGeo];
+#pragma unroll
+    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[i * K + k];
+    const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
+                tz = gg[8];
+    const float rc2 = gg[9], irho = gg[10];
+
+    v4f cp[NR], w0[NR], w1[NR], w2[NR];
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int c = 0; c < NK; ++c) {
+      v4s urh, url, ush, usl, uth, utl, ph, pl;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int mm = 16 * c + 4 * g + v;
+        float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+        if (mm < Np) {
+          p = a.q[(int64_t)mm * K + k];
+          vx = a.q[(int64_t)(Np + mm) * K + k];
+          vy = a.q[(int64_t)(2 * Np + mm) * K + k];
+          vz = a.q[(int64_t)(3 * Np + mm) * K + k];
+        }
+        short h, l;
+        split_bf16(rx * vx + ry * vy + rz * vz, h, l); urh[v] = h; url[v] = l;
+        split_bf16(sx * vx + sy * vy + sz * vz, h, l); ush[v] = h; usl[v] = l;
+        split_bf16(tx * vx + ty * vy + tz * vz, h, l); uth[v] = h; utl[v] = l;
+        split_bf16(p, h, l); ph[v] = h; pl[v] = l;
+      }
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) {
-        rp[rt] = -rp[rt]; rvx[rt] = -rvx[rt]; rvy[rt] = -rvy[rt]; rvz[rt] = -rvz[rt];
+        const uint4 ar = fD[((0 * NR + rt) * NK + c) * 64 + lane];
+        const uint4 as = fD[((1 * NR + rt) * NK + c) * 64 + lane];
+        const uint4 at = fD[((2 * NR + rt) * NK + c) * 64 + lane];
+#define MF(A, B, C) C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, C, 0, 0, 0)
+        MF(hi(ar), urh, cp[rt]); MF(hi(ar), url, cp[rt]); MF(lo(ar), urh, cp[rt]);
+        MF(hi(as), ush, cp[rt]); MF(hi(as), usl, cp[rt]); MF(lo(as), ush, cp[rt]);
+        MF(hi(at), uth, cp[rt]); MF(hi(at), utl, cp[rt]); MF(lo(at), uth, cp[rt]);
+        MF(hi(ar), ph, w0[rt]); MF(hi(ar), pl, w0[rt]); MF(lo(ar), ph, w0[rt]);
+        MF(hi(as), ph, w1[rt]); MF(hi(as), pl, w1[rt]); MF(lo(as), ph, w1[rt]);
+        MF(hi(at), ph, w2[rt]); MF(hi(at), pl, w2[rt]); MF(lo(at), ph, w2[rt]);
       }
     }
+    v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
+    volume_to_rhs<NR>(gg, cp, w0, w1, w2, rp, rvx, rvy, rvz);
 
-    // ---- point sources (projected delta into the pressure equation)
-    if (valid && (flag & 4)) {
-      const int s0 = a.src_start[k], scn = a.src_count[k];
-      for (int en = s0; en < s0 + scn; ++en) {
-        const int pt = a.src_point[en];
-        float amp = 0.0f;
-        if (a.amp_mode == 0) {
-          amp = a.wavelet[a.tau];
-        } else {
-          const int64_t j = a.data_j;
-          const int64_t gq = j / a.n_local, rem = j % a.n_local;
-          if (j >= 0 && (gq < a.n_t - 1 || (gq == a.n_t - 1 && rem == 0))) {
-            const float *d = a.data + (int64_t)pt * a.n_t;
-            if (rem == 0) amp = d[gq];
-            else {
-              const float th = (float)rem / (float)a.n_local;
-              amp = (1.0f - th) * d[gq] + th * d[gq + 1];
-            }
+    float nfx[4], nfy[4], nfz[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const FaceCtx fc = face_ctx<N>(a, f, k, gg);
+      nfx[f] = fc.nx; nfy[f] = fc.ny; nfz[f] = fc.nz;
+      v4f G[NR];
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int cc = 0; cc < FC; ++cc) {
+        v4s pph, ppl, pvh, pvl;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int s = 16 * cc + 4 * g + v;
+          float mPp = 0.f, Pv = 0.f;
+          if (16 * cc + 12 + v < Nfp || s < Nfp) {
+            const int node = sel4(g, T.fmask[f][min(16 * cc + v, Nfp - 1)], T.fmask[f][min(16 * cc + 4 + v, Nfp - 1)],
+                                  T.fmask[f][min(16 * cc + 8 + v, Nfp - 1)], T.fmask[f][min(16 * cc + 12 + v, Nfp - 1)]);
+            penalty<N>(a, fc, s, node, k, rc2, irho, mPp, Pv);
           }
+          short h, l;
+          split_bf16(mPp, h, l); pph[v] = h; ppl[v] = l;
+          split_bf16(Pv, h, l); pvh[v] = h; pvl[v] = l;
         }
-        amp *= a.src_scale;
-        const float *w = a.src_w + (int64_t)pt * Np;
 #pragma unroll
-        for (int rt = 0; rt < NR; ++rt)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int n = 16 * rt + 4 * g + i;
-            if (16 * rt + 15 < Np || n < Np) rp[rt][i] += amp * w[n];
-          }
+        for (int rt = 0; rt < NR; ++rt) {
+          const uint4 al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
+          MF(hi(al), pph, rp[rt]); MF(hi(al), ppl, rp[rt]); MF(lo(al), pph, rp[rt]);
+          MF(hi(al), pvh, G[rt]); MF(hi(al), pvl, G[rt]); MF(lo(al), pvh, G[rt]);
+#undef MF
+        }
       }
-    }
-
-    if constexpr (MODE == MODE_RHS_ONLY) {
-      if (valid) {
 #pragma unroll
-        for (int rt = 0; rt < NR; ++rt)
+      for (int rt = 0; rt < NR; ++rt)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int n = 16 * rt + 4 * g + i;
-            if (16 * rt + 15 < Np || n < Np) {
-              a.rhs_out[(int64_t)(0 * Np + n) * K + k] = rp[rt][i];
-              a.rhs_out[(int64_t)(1 * Np + n) * K + k] = rvx[rt][i];
-              a.rhs_out[(int64_t)(2 * Np + n) * K + k] = rvy[rt][i];
-              a.rhs_out[(int64_t)(3 * Np + n) * K + k] = rvz[rt][i];
-            }
-          }
-      }
-      continue;
-    }
-
-    // ---- AB3 update, rhs ring, traces of the new state (and of the half step for coarse neighbours)
-    const float dtl = (float)(a.dt_local * (double)(1LL << sh));
-    float *__restrict__ R0 = a.ring + (m % 3) * slab;
-    const float *__restrict__ R1 = a.ring + ((m + 2) % 3) * slab;
-    const float *__restrict__ R2 = a.ring + ((m + 1) % 3) * slab;
-    float *__restrict__ trw = a.tr + ((m + 1) & 1) * (int64_t)2 * F * K;
-    float *__restrict__ trm = a.tr + (int64_t)2 * 2 * F * K;
-    const bool mid = (flag & 2) != 0;
-    float *q = a.q;
-    const float ux = a.up[0], uy = a.up[1], uz = a.up[2];
-    const float zs = a.condition ? Z : 0.0f;
-    int64_t kk = 0, Pl = 0, jS = 0;
-    bool do_img = false;
-    if constexpr (MODE == MODE_RECORD_SEG || MODE == MODE_IMAGE) {
-      kk = k - a.lev_begin[lev - 1];
-      Pl = level_end(a.lev_begin, a.L, lev) - a.lev_begin[lev - 1];
-    }
-    if constexpr (MODE == MODE_RECORD_SEG) jS = m - a.seg_m0[lev - 1];
-    if constexpr (MODE == MODE_IMAGE) {
-      const int64_t mS = a.own_total[lev - 1] - m - 1;
-      jS = mS - a.seg_m0[lev - 1];
-      do_img = (mS << sh) >= a.image_from && jS >= 0 && jS < a.seg_len[lev - 1];
-    }
-    const double dtd = a.dt_local * (double)(1LL << sh);
-    if (!valid) continue;
-
-#pragma unroll
-    for (int rt = 0; rt < NR; ++rt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int n = 16 * rt + 4 * g + i;
-        if (!(16 * rt + 15 < Np || n < Np)) continue;
-        const float r[4] = {rp[rt][i], rvx[rt][i], rvy[rt][i], rvz[rt][i]};
-        float qo[4], h1[4], h2[4], qn[4], qm[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t idx = (int64_t)(c * Np + n) * K + k;
-          h1[c] = R1[idx];
-          h2[c] = R2[idx];
-          qo[c] = q[idx];
-          R0[idx] = r[c];
-          qn[c] = qo[c] + dtl * (kA0 * r[c] + kA1 * h1[c] + kA2 * h2[c]);
-          q[idx] = qn[c];
-          qm[c] = qo[c] + dtl * (kB0 * r[c] + kB1 * h1[c] + kB2 * h2[c]);
+        for (int i = 0; i < 4; ++i) {
+          rvx[rt][i] -= fc.nx * G[rt][i];
+          rvy[rt][i] -= fc.ny * G[rt][i];
+          rvz[rt][i] -= fc.nz * G[rt][i];
         }
-        if constexpr (MODE == MODE_RECORD_SEG) {
-          const float qminus = qo[0] - zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
-          const float rminus = r[0] - zs * (ux * r[1] + uy * r[2] + uz * r[3]);
-          a.seg_q[a.seg_q_off[lev - 1] + (jS * Np + n) * Pl + kk] = qminus;
-          a.seg_r[a.seg_r_off[lev - 1] + ((jS + 2) * Np + n) * Pl + kk] = rminus;
-        }
-        if constexpr (MODE == MODE_IMAGE) {
-          if (do_img) {
-            const float *sq = a.seg_q + a.seg_q_off[lev - 1];
-            const float *sr = a.seg_r + a.seg_r_off[lev - 1];
-            const double qS = sq[(jS * Np + n) * Pl + kk];
-            const double rS[3] = {sr[((jS + 2) * Np + n) * Pl + kk], sr[((jS + 1) * Np + n) * Pl + kk],
-                                  sr[(jS * Np + n) * Pl + kk]};
-            const double qR = qo[0] + zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
-            const double rR[3] = {r[0] + zs * (ux * r[1] + uy * r[2] + uz * r[3]),
-                                  h1[0] + zs * (ux * h1[1] + uy * h1[2] + uz * h1[3]),
-                                  h2[0] + zs * (ux * h2[1] + uy * h2[2] + uz * h2[3])};
-            double inc2 = 0.0, inc3 = 0.0;
-#pragma unroll
-            for (int s = 0; s < 3; ++s) inc2 += kE[s] * (qS * rR[s] + rS[s] * qR);
-#pragma unroll
-            for (int s1 = 0; s1 < 3; ++s1)
-#pragma unroll
-              for (int s2 = 0; s2 < 3; ++s2) inc3 += kCm[s1][s2] * rS[s1] * rR[s2];
-            a.img[(int64_t)n * K + k] += dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
-          }
-        }
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          const int fi = sel4(g, T.fidx[min(16 * rt + i, Np - 1)][f], T.fidx[min(16 * rt + 4 + i, Np - 1)][f],
-                              T.fidx[min(16 * rt + 8 + i, Np - 1)][f], T.fidx[min(16 * rt + 12 + i, Np - 1)][f]);
-          if (fi >= 0) {
-            const int64_t r0 = (int64_t)(f * Nfp + fi) * K + k;
-            const int64_t r1 = (int64_t)(F + f * Nfp + fi) * K + k;
-            trw[r0] = qn[0];
-            trw[r1] = nfx[f] * qn[1] + nfy[f] * qn[2] + nfz[f] * qn[3];
-            if (mid) {
-              trm[r0] = qm[0];
-              trm[r1] = nfx[f] * qm[1] + nfy[f] * qm[2] + nfz[f] * qm[3];
-            }
-          }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    tile_tail<N, MODE>(a, k, g, lev, sh, m, flag, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
   }
 }
 
@@ -532,22 +730,38 @@ __global__ void fill_f64_kernel(double *p, int64_t n, double v) {
 // ------------------------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+template <class KernelFn>
+static hipError_t ensure_lds(KernelFn fn, size_t lds, bool &done) {
+  if (lds > 64 * 1024 && !done) {
+    hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  done = true;
+  return hipSuccess;
+}
+
 template <int N, int MODE>
 static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
   const int64_t groups = (a.k_end / 16 + 3) / 4;
   const int64_t cap = a.max_groups > 0 ? a.max_groups : groups;
   const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, cap))), block(256);
+  if (a.precision == 1) {
+    constexpr size_t lds = (size_t)DimsB<N>::OPS_U4 * sizeof(uint4);
+    if constexpr (lds <= 96 * 1024) {
+      static bool done = false;
+      hipError_t e = ensure_lds(step_kernel_bf16<N, MODE, true>, lds, done);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((step_kernel_bf16<N, MODE, true>), grid, block, lds, st, a);
+    } else {
+      hipLaunchKernelGGL((step_kernel_bf16<N, MODE, false>), grid, block, 0, st, a);
+    }
+    return hipGetLastError();
+  }
   constexpr size_t lds = Dims<N>::OPS * sizeof(float);
   if constexpr (lds <= 96 * 1024) {
-    if constexpr (lds > 64 * 1024) {
-      static bool attr_done = false;
-      if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void *)step_kernel<N, MODE, true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-      }
-    }
+    static bool done = false;
+    hipError_t e = ensure_lds(step_kernel<N, MODE, true>, lds, done);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((step_kernel<N, MODE, true>), grid, block, lds, st, a);
   } else {
     hipLaunchKernelGGL((step_kernel<N, MODE, false>), grid, block, 0, st, a);
@@ -584,6 +798,68 @@ void build_op_fragments(int N, const float *Dr, const float *Ds, const float *Dt
           const int row = 16 * rt + (l & 15), s = 4 * cc + (l >> 4);
           L[(rt * 4 * FC + f * FC + cc) * 64 + l] = (row < Np && s < Nfp) ? LIFT[row * F + f * Nfp + s] : 0.0f;
         }
+}
+
+static uint16_t host_bf16(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+static float host_bf16_value(uint16_t h) {
+  const uint32_t b = (uint32_t)h << 16;
+  float x;
+  std::memcpy(&x, &b, 4);
+  return x;
+}
+
+void build_op_fragments_bf16(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
+                             uint32_t *out) {
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2, F = 4 * Nfp;
+  const int NR = (Np + 15) / 16, NK = (Np + 15) / 16, FC = (Nfp + 15) / 16;
+  auto put = [&](uint32_t *u, const double *vals) {  // 4 values -> hi pair, lo pair
+    uint16_t h[4], l[4];
+    for (int v = 0; v < 4; ++v) {
+      h[v] = host_bf16((float)vals[v]);
+      l[v] = host_bf16((float)(vals[v] - (double)host_bf16_value(h[v])));
+    }
+    u[0] = h[0] | ((uint32_t)h[1] << 16);
+    u[1] = h[2] | ((uint32_t)h[3] << 16);
+    u[2] = l[0] | ((uint32_t)l[1] << 16);
+    u[3] = l[2] | ((uint32_t)l[3] << 16);
+  };
+  const double *D[3] = {Dr, Ds, Dt};
+  for (int j = 0; j < 3; ++j)
+    for (int rt = 0; rt < NR; ++rt)
+      for (int c = 0; c < NK; ++c)
+        for (int l = 0; l < 64; ++l) {
+          const int row = 16 * rt + (l & 15);
+          double vals[4];
+          for (int v = 0; v < 4; ++v) {
+            const int col = 16 * c + 4 * (l >> 4) + v;
+            vals[v] = (row < Np && col < Np) ? D[j][row * Np + col] : 0.0;
+          }
+          put(out + 4 * (((j * NR + rt) * NK + c) * 64 + l), vals);
+        }
+  uint32_t *L = out + 4 * (3 * NR * NK * 64);
+  for (int rt = 0; rt < NR; ++rt)
+    for (int f = 0; f < 4; ++f)
+      for (int cc = 0; cc < FC; ++cc)
+        for (int l = 0; l < 64; ++l) {
+          const int row = 16 * rt + (l & 15);
+          double vals[4];
+          for (int v = 0; v < 4; ++v) {
+            const int s = 16 * cc + 4 * (l >> 4) + v;
+            vals[v] = (row < Np && s < Nfp) ? LIFT[row * F + f * Nfp + s] : 0.0;
+          }
+          put(L + 4 * ((rt * 4 * FC + f * FC + cc) * 64 + l), vals);
+        }
+}
+
+int64_t op_fragment_bf16_words(int N) {
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
+  const int NR = (Np + 15) / 16, NK = (Np + 15) / 16, FC = (Nfp + 15) / 16;
+  return (int64_t)(3 * NR * NK + NR * 4 * FC) * 64 * 4;
 }
 
 int64_t op_fragment_floats(int N) {

@@ -27,7 +27,9 @@ struct StepArgs {
   const int *nbr;
   const int *ncode;
   const int *eflag;
-  const float *ops;                   // operator fragments (build_op_fragments)
+  const float *ops;                   // FP32 operator fragments (build_op_fragments)
+  const uint32_t *ops_bf16;           // split-BF16 operator fragments (build_op_fragments_bf16)
+  int precision;                      // 0 FP32 MFMA, 1 split-BF16 MFMA
   const int8_t *nbr_index;            // [4][4][6][Nfp]
   int64_t Ktot;
   int L;                              // number of levels
@@ -70,6 +72,10 @@ hipError_t launch_step(int N, const StepArgs &a, hipStream_t st);
 // operator fragments in MFMA lane order from row-major Dr, Ds, Dt (Np x Np) and LIFT (Np x 4Nfp)
 void build_op_fragments(int N, const float *Dr, const float *Ds, const float *Dt, const float *LIFT, float *out);
 int64_t op_fragment_floats(int N);
+// hi/lo bf16 operator fragments for the split-BF16 kernel, built from the FP64 operators
+void build_op_fragments_bf16(int N, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
+                             uint32_t *out);
+int64_t op_fragment_bf16_words(int N);
 
 struct TraceInitArgs {
   const float *q;

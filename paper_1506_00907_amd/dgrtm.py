@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdgrtm.so")
 
 BC_RIGID, BC_TRANSPARENT, BC_FREE = 1, 2, 3
 IMAGE_PRESSURE, IMAGE_CHARACTERISTIC = 0, 1
+FP32, SPLIT_BF16 = 0, 1
 SOURCE_FIELD, RECEIVER_FIELD = 0, 1
 
 _SYMBOLS = {
@@ -54,7 +55,8 @@ class ShotArgs(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("has_source", C.c_int32), ("src_xyz", C.c_double * 3),
                 ("f_peak", C.c_double), ("t_peak", C.c_double), ("amp", C.c_double),
                 ("wavelet", C.c_void_p), ("n_rec", C.c_int64), ("rec_xyz", C.c_void_p),
-                ("t_final", C.c_double), ("ckpt_interval", C.c_int64)]
+                ("t_final", C.c_double), ("ckpt_interval", C.c_int64), ("precision", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -175,6 +177,7 @@ class ShotSpec:
     rec: np.ndarray | None = None
     wavelet: np.ndarray | None = None
     ckpt_interval: int = 0
+    precision: int = 0
 
 
 class Shot:
@@ -200,6 +203,7 @@ class Shot:
         a.rec_xyz = None if self._rec is None else _ptr(self._rec)
         a.t_final = float(spec.t_final)
         a.ckpt_interval = int(spec.ckpt_interval)
+        a.precision = int(spec.precision)
         self.args = a
         ng, nl = C.c_int64(), C.c_int32()
         _check(_lib.dgrtm_shot_steps(mesh.h, C.byref(a), C.byref(ng), C.byref(nl)), "dgrtm_shot_steps")

@@ -137,3 +137,59 @@ def test_residual_fp64():
     r = shot.residual(dev(a), dev(b))
     ref = np.sum((a.astype(np.float64) - b.astype(np.float64)) ** 2)
     assert abs(r - ref) < 1e-12 * ref
+
+
+@pytest.mark.parametrize("name", ["two_layer_small:4:4:3:3", "two_layer_small:4:3:3:4", "two_layer_small:3:3:2:5"])
+def test_rhs_parity_split_bf16(name):
+    from paper_1506_00907_amd import dgrtm
+    mm, rho, c, N = I.config_mesh(name)
+    lm = dgrtm.Mesh(N, mm.verts, mm.etov).set_model(rho, c, n_levels_max=3).bind("cuda")
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=lm.dt_local, precision=dgrtm.SPLIT_BF16))
+    from oracle.dg import Operator
+    m, op, *_ = case(name)
+    rng = np.random.default_rng(5)
+    # a smooth field plus noise: the relevant case for error growth
+    x = op.m.x
+    q = np.stack([np.sin(2 * x[..., 0]) * np.cos(x[..., 1] + x[..., 2])] * 4, axis=1)
+    q += 0.01 * rng.standard_normal(q.shape)
+    got = shot.apply_rhs(dev(q)).cpu().numpy()
+    err = rel(got, op.rhs(q))
+    assert err < 1e-4, err
+
+
+@pytest.mark.parametrize("name,nl", [("two_layer_small:5:5:3:4", 3)])
+def test_split_bf16_forward_100_steps(name, nl):
+    from paper_1506_00907_amd import dgrtm
+    lm, mm, rho, c, N = lib_mesh(name, BC_TRANSPARENT, nl)
+    m, op, lev, L, dtl = case(name, bc=BC_TRANSPARENT, n_levels=nl)
+    spec = I.rtm_shot(n_rec=5)
+    spec.t_peak = 0.02
+    ng = 100 // (2 ** (L - 1)) + 1
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=ng * dtl * 2 ** (L - 1), src=spec.src, f_peak=spec.f_peak,
+                                         t_peak=spec.t_peak, rec=spec.rec, precision=dgrtm.SPLIT_BF16))
+    tr = shot.forward().cpu().numpy()
+    q = shot.get_state(dgrtm.SOURCE_FIELD).cpu().numpy()
+    osh = _oracle_shot(name, lev, L, dtl, op, ng, spec)
+    tr_ref = osh.forward(keep=False)
+    assert rel(q, osh.S_final) < 1e-4
+    assert rel(tr, tr_ref) < 1e-4
+
+
+def test_split_bf16_image():
+    from paper_1506_00907_amd import dgrtm
+    name = "two_layer_small:6:6:4:2"
+    lm, mm, rho, c, N = lib_mesh(name, BC_TRANSPARENT, 3)
+    m, op, lev, L, dtl = case(name, bc=BC_TRANSPARENT, n_levels=3)
+    spec = I.rtm_shot(n_rec=4)
+    spec.t_peak = 0.03
+    ng = 30
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=ng * dtl * 2 ** (L - 1), src=spec.src, f_peak=spec.f_peak,
+                                         t_peak=spec.t_peak, rec=spec.rec, ckpt_interval=4,
+                                         precision=dgrtm.SPLIT_BF16))
+    tr = shot.forward()
+    shot.adjoint(tr, condition=COND_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start=0)
+    img = shot.image().cpu().numpy()
+    osh = _oracle_shot(name, lev, L, dtl, op, ng, spec)
+    osh.forward()
+    img_ref = osh.adjoint(tr.cpu().numpy().astype(np.float64))
+    assert rel(img, img_ref) < 1e-4

@@ -105,3 +105,22 @@ def test_errors_are_reported():
     lm = dgrtm.Mesh(3, m.verts, m.etov)
     with pytest.raises(dgrtm.DgrtmError, match="positive"):
         lm.set_model(np.ones(m.K), -np.ones(m.K))
+
+
+def test_shot_args_struct_matches_c_layout():
+    # dgrtm_shot_steps is host-only and rejects a struct_size that differs from the C struct
+    import ctypes as C
+    from paper_1506_00907_amd import dgrtm
+    m = I.unit_cube_mesh(2)
+    lm = dgrtm.Mesh(3, m.verts, m.etov).set_model(np.ones(m.K), np.ones(m.K), 2)
+    a = dgrtm.ShotArgs()
+    a.struct_size = C.sizeof(dgrtm.ShotArgs)
+    a.t_final = 0.1
+    ng, nl = C.c_int64(), C.c_int32()
+    assert dgrtm._lib.dgrtm_shot_steps(lm.h, C.byref(a), C.byref(ng), C.byref(nl)) == 0
+    assert ng.value == int(np.ceil(0.1 / (lm.dt_local * nl.value) - 1e-9)) and nl.value == 2 ** (lm.L - 1)
+    a.struct_size -= 8
+    assert dgrtm._lib.dgrtm_shot_steps(lm.h, C.byref(a), C.byref(ng), C.byref(nl)) != 0
+    a.struct_size += 8
+    a.precision = 7
+    assert dgrtm._lib.dgrtm_shot_steps(lm.h, C.byref(a), C.byref(ng), C.byref(nl)) != 0
