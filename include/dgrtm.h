@@ -183,6 +183,38 @@ dgrtm_status dgrtm_forward(dgrtm_shot shot, float *traces_out);
 dgrtm_status dgrtm_adjoint(dgrtm_shot shot, const float *data, int condition, const double *up,
                            int64_t g_image_start);
 
+/* ---- continuous batching: several shots of one mesh advanced together ---- */
+
+/* phases of a shot's pipeline (dgrtm_shot_state) */
+#define DGRTM_PHASE_IDLE 0
+#define DGRTM_PHASE_FORWARD 1
+#define DGRTM_PHASE_RECOMPUTE 2
+#define DGRTM_PHASE_BACKWARD 3
+#define DGRTM_PHASE_DONE 4
+
+/*
+ * Reset a shot to run its whole RTM pipeline through dgrtm_step_shots: the forward run, then the
+ * adjoint (segment recompute and backward run with imaging) with the given parameters (as for
+ * dgrtm_adjoint).  data = NULL uses the shot's own recorded traces as the data.  Enqueues the
+ * state reset only.
+ */
+dgrtm_status dgrtm_shot_begin(dgrtm_shot shot, const float *data, int condition, const double *up,
+                              int64_t g_image_start);
+
+/*
+ * Advance each of n shots (all on one mesh and bound to one stream) by n_global global steps of
+ * its pipeline; shots that are idle or done are skipped.  Shots that are at the same step mode
+ * (forward, recompute or backward-with-image) and precision share one kernel launch per local
+ * step (up to 8 per launch), each with its own time index, sources and buffers.  Asynchronous.
+ */
+dgrtm_status dgrtm_step_shots(dgrtm_shot *shots, int n, int64_t n_global);
+
+/* Copy the shot's recorded traces (n_rec x (n_global + 1) floats) into out (device). */
+dgrtm_status dgrtm_shot_traces(dgrtm_shot shot, float *out);
+
+/* Host-side pipeline state: phase (DGRTM_PHASE_*), global steps done and in total. */
+dgrtm_status dgrtm_shot_state(dgrtm_shot shot, int *phase, int64_t *steps_done, int64_t *steps_total);
+
 /* Copy (accumulate = 0) or add (accumulate = 1) the FP64 image into image_out (device, n_elem x Np). */
 dgrtm_status dgrtm_image(dgrtm_shot shot, double *image_out, int accumulate);
 

@@ -88,6 +88,16 @@ struct dgrtm_shot_s {
   float *traces = nullptr;     // n_rec x (n_global + 1)
   double *red = nullptr;       // FP64 reduction scratch
   bool forward_done = false;
+  // pipeline state, advanced one global step at a time (dgrtm_step_shots)
+  int ph = DGRTM_PHASE_IDLE;
+  int64_t g = 0;               // forward / recompute: next global step of the source field
+  int64_t c = 0, g0 = 0, g1 = 0;  // adjoint: current segment [g0, g1)
+  int64_t gr = 0, gr_end = 0;  // adjoint: next / last+1 global step of the receiver field in this segment
+  bool full_rtm = false;       // run the adjoint right after the forward (serving)
+  const float *data = nullptr;
+  int condition = DGRTM_IMAGE_CHARACTERISTIC;
+  float up[3] = {0.f, 0.f, 1.f};
+  int64_t g_image_start = 0;
   // sampled HIP-event timing of the step kernel (dgrtm_profile_*)
   int prof_every = 0;
   int64_t prof_counter = 0;
@@ -511,30 +521,25 @@ static void fill_level_begin(const HostMesh &h, int64_t *lb) {
   for (int l = 0; l <= h.L; ++l) lb[l] = h.lev_begin[l];
 }
 
-static StepArgs base_args(dgrtm_shot sh, Field &f, bool reversed) {
-  dgrtm_mesh m = sh->mesh;
+static StepArgs mesh_args(dgrtm_mesh m, int precision, int mode, bool reversed, int n_local) {
   const HostMesh &h = m->hm;
   StepArgs a;
   std::memset(&a, 0, sizeof(a));
   a.geo = m->geo;
   a.nbr = m->nbr;
   a.ncode = m->ncode;
-  a.eflag = m->eflag;
   a.ops = m->ops;
   a.ops_bf16 = m->ops_bf16;
-  a.precision = sh->args.precision;
   a.nbr_index = m->nbr_index;
   a.Ktot = h.Ktot;
   a.L = h.L;
   fill_level_begin(h, a.lev_begin);
-  a.q = f.q;
-  a.ring = f.ring;
-  a.tr = f.tr;
   a.dt_local = h.dt_local;
   a.tau_sign = reversed ? -1.0f : 1.0f;
   a.out_sign = reversed ? -1.0f : 1.0f;
-  a.n_local = sh->n_local;
-  a.up[2] = 1.0f;
+  a.n_local = n_local;
+  a.precision = precision;
+  a.mode = mode;
   return a;
 }
 
@@ -543,6 +548,14 @@ static int64_t active_end(const HostMesh &h, int64_t tau) {
   for (int l = 1; l <= h.L; ++l)
     if ((tau & (((int64_t)1 << (h.L - l)) - 1)) == 0) return level_end_h(h, l);
   return level_end_h(h, h.L);
+}
+
+// real elements in the active prefix [0, k_end)
+static int64_t active_elements(const HostMesh &h, int64_t k_end) {
+  int64_t n = 0;
+  for (int l = 1; l <= h.L; ++l)
+    if (h.lev_begin[l - 1] < k_end) n += h.lev_count[l - 1];
+  return n;
 }
 
 static dgrtm_status trace_init(dgrtm_shot sh, Field &f) {
@@ -572,23 +585,11 @@ static dgrtm_status zero_field(dgrtm_shot sh, Field &f) {
   return DGRTM_OK;
 }
 
-static int step_mode(const StepArgs &a) {
-  return a.rhs_out ? MODE_RHS_ONLY : a.img ? MODE_IMAGE : a.seg_q ? MODE_RECORD_SEG : MODE_PLAIN;
-}
-
-// real elements in the active prefix [0, k_end)
-static int64_t active_elements(const HostMesh &h, int64_t k_end) {
-  int64_t n = 0;
-  for (int l = 1; l <= h.L; ++l)
-    if (h.lev_begin[l - 1] < k_end) n += h.lev_count[l - 1];
-  return n;
-}
-
-// one local step of a field: a is prepared by the caller except tau / k_end
-static dgrtm_status local_step(dgrtm_shot sh, Field &f, StepArgs &a) {
-  dgrtm_mesh m = sh->mesh;
-  a.tau = f.tau;
-  a.k_end = active_end(m->hm, f.tau);
+// Launch one local step for `n` slots (same mesh, mode and local phase), timing it if sampled.
+static dgrtm_status launch_slots(dgrtm_shot prof_owner, StepArgs &a, int64_t tau) {
+  dgrtm_mesh m = prof_owner->mesh;
+  a.k_end = active_end(m->hm, tau);
+  dgrtm_shot sh = prof_owner;
   const bool prof = sh->prof_every > 0 && (sh->prof_counter++ % sh->prof_every) == 0;
   size_t ev = 0;
   if (prof) {
@@ -603,9 +604,8 @@ static dgrtm_status local_step(dgrtm_shot sh, Field &f, StepArgs &a) {
   HIPCHK(launch_step(m->ref.N, a, m->stream));
   if (prof) {
     HIPCHK(hipEventRecord(sh->prof_ev[ev + 1], m->stream));
-    sh->prof_rec.push_back({step_mode(a), active_elements(m->hm, a.k_end), ev});
+    sh->prof_rec.push_back({a.mode, active_elements(m->hm, a.k_end) * a.nslots, ev});
   }
-  f.tau += 1;
   return DGRTM_OK;
 }
 
@@ -637,14 +637,67 @@ extern "C" dgrtm_status dgrtm_profile_read(dgrtm_shot sh, int mode, double *kern
   return DGRTM_OK;
 }
 
-static void set_source(StepArgs &a, const PointSet &p, int amp_mode) {
-  a.eflag = p.eflag;
-  a.src_start = p.start;
-  a.src_count = p.count;
-  a.src_point = p.point;
-  a.src_w = p.w;
-  a.amp_mode = amp_mode;
-  a.src_scale = 1.0f;
+static SlotArgs field_slot(dgrtm_shot sh, Field &f) {
+  SlotArgs s;
+  std::memset(&s, 0, sizeof(s));
+  s.q = f.q;
+  s.ring = f.ring;
+  s.tr = f.tr;
+  s.eflag = sh->mesh->eflag;
+  s.tau = f.tau;
+  s.up[2] = 1.0f;
+  s.src_scale = 1.0f;
+  s.C = sh->C;
+  s.NG = sh->n_global;
+  return s;
+}
+
+static void with_points(SlotArgs &s, const PointSet &p, int amp_mode) {
+  if (p.n == 0) return;
+  s.eflag = p.eflag;
+  s.src_start = p.start;
+  s.src_count = p.count;
+  s.src_point = p.point;
+  s.src_w = p.w;
+  s.amp_mode = amp_mode;
+}
+
+// the slot of a shot for its next global step, and the step mode
+static SlotArgs phase_slot(dgrtm_shot sh, int &mode, bool &reversed, Field *&field) {
+  SlotArgs s;
+  if (sh->ph == DGRTM_PHASE_BACKWARD) {
+    field = &sh->R;
+    s = field_slot(sh, sh->R);
+    with_points(s, sh->rec, 1);
+    s.data = sh->data ? sh->data : sh->traces;
+    s.n_t = sh->n_global + 1;
+    s.src_scale = -1.0f;
+    s.seg_q = sh->seg_q;
+    s.seg_r = sh->seg_r;
+    s.img = sh->img;
+    s.g0 = sh->g0;
+    s.g1 = sh->g1;
+    s.image_from = sh->g_image_start * sh->n_local;
+    mode = MODE_IMAGE;
+    reversed = true;
+  } else {
+    field = &sh->S;
+    s = field_slot(sh, sh->S);
+    if (sh->args.has_source) with_points(s, sh->src, 0);
+    s.wavelet = sh->wavelet;
+    mode = MODE_PLAIN;
+    reversed = false;
+    if (sh->ph == DGRTM_PHASE_RECOMPUTE) {
+      s.seg_q = sh->seg_q;
+      s.seg_r = sh->seg_r;
+      s.g0 = sh->g0;
+      s.g1 = sh->g1;
+      mode = MODE_RECORD_SEG;
+    }
+  }
+  std::memcpy(s.up, sh->up, sizeof(s.up));
+  s.condition = sh->condition;
+  return s;
 }
 
 static dgrtm_status record(dgrtm_shot sh, Field &f, int64_t g) {
@@ -682,105 +735,240 @@ static dgrtm_status ckpt_copy(dgrtm_shot sh, Field &f, int64_t c, bool save) {
   return DGRTM_OK;
 }
 
+// start segment c of the adjoint: restore S at g0 and prepare its segment buffer history
+static dgrtm_status begin_segment(dgrtm_shot sh, int64_t c) {
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  dgrtm_status s;
+  sh->c = c;
+  sh->g0 = c * sh->C;
+  sh->g1 = std::min(sh->n_global, sh->g0 + sh->C);
+  sh->g = sh->g0;
+  if ((s = ckpt_copy(sh, sh->S, c, false))) return s;
+  sh->S.tau = sh->g0 * sh->n_local;
+  if ((s = trace_init(sh, sh->S))) return s;
+  SegInitArgs si;
+  std::memset(&si, 0, sizeof(si));
+  si.ring = sh->S.ring;
+  si.geo = m->geo;
+  si.eflag = m->eflag;
+  si.seg_r = sh->seg_r;
+  si.Ktot = h.Ktot;
+  si.L = h.L;
+  fill_level_begin(h, si.lev_begin);
+  std::memcpy(si.up, sh->up, sizeof(si.up));
+  si.condition = sh->condition;
+  for (int l = 1; l <= h.L; ++l) {
+    si.seg_r_off[l - 1] = sh->seg_r_off[l - 1];
+    si.seg_m0[l - 1] = sh->g0 << (l - 1);
+  }
+  HIPCHK(launch_seg_init(m->ref.N, si, m->stream));
+  sh->gr = sh->n_global - sh->g1;
+  sh->gr_end = sh->n_global - std::max(sh->g0, sh->g_image_start);
+  sh->ph = DGRTM_PHASE_RECOMPUTE;
+  return DGRTM_OK;
+}
+
+static dgrtm_status begin_forward(dgrtm_shot sh) {
+  dgrtm_status s;
+  if ((s = zero_field(sh, sh->S))) return s;
+  if ((s = record(sh, sh->S, 0))) return s;
+  sh->g = 0;
+  sh->forward_done = false;
+  sh->ph = DGRTM_PHASE_FORWARD;
+  return DGRTM_OK;
+}
+
+static dgrtm_status begin_adjoint(dgrtm_shot sh) {
+  dgrtm_mesh m = sh->mesh;
+  dgrtm_status s;
+  HIPCHK(launch_fill_f64(sh->img, (int64_t)m->ref.Np * m->hm.Ktot, 0.0, m->stream));
+  if ((s = zero_field(sh, sh->R))) return s;
+  return begin_segment(sh, (sh->n_global - 1) / sh->C);
+}
+
+// work before a global step of the shot's current phase
+static dgrtm_status pre_global(dgrtm_shot sh) {
+  if (sh->ph == DGRTM_PHASE_FORWARD && sh->g % sh->C == 0) return ckpt_copy(sh, sh->S, sh->g / sh->C, true);
+  return DGRTM_OK;
+}
+
+// work after a global step: recording, phase transitions
+static dgrtm_status post_global(dgrtm_shot sh) {
+  dgrtm_status s;
+  switch (sh->ph) {
+    case DGRTM_PHASE_FORWARD:
+      sh->g += 1;
+      if ((s = record(sh, sh->S, sh->g))) return s;
+      if (sh->g == sh->n_global) {
+        sh->forward_done = true;
+        sh->ph = DGRTM_PHASE_IDLE;
+        if (sh->full_rtm) return begin_adjoint(sh);
+      }
+      return DGRTM_OK;
+    case DGRTM_PHASE_RECOMPUTE:
+      sh->g += 1;
+      if (sh->g == sh->g1) sh->ph = DGRTM_PHASE_BACKWARD;
+      return DGRTM_OK;
+    case DGRTM_PHASE_BACKWARD:
+      sh->gr += 1;
+      if (sh->gr == sh->gr_end) {
+        if (sh->c - 1 >= sh->g_image_start / sh->C && sh->c > 0) return begin_segment(sh, sh->c - 1);
+        sh->ph = DGRTM_PHASE_DONE;
+      }
+      return DGRTM_OK;
+    default:
+      return DGRTM_OK;
+  }
+}
+
+static bool stepping(const dgrtm_shot sh) {
+  return sh->ph == DGRTM_PHASE_FORWARD || sh->ph == DGRTM_PHASE_RECOMPUTE || sh->ph == DGRTM_PHASE_BACKWARD;
+}
+
+// one global step of every stepping shot; shots of one mesh at the same mode share launches
+static dgrtm_status global_step_shots(dgrtm_shot *shots, int n) {
+  dgrtm_status s;
+  std::vector<dgrtm_shot> act;
+  for (int i = 0; i < n; ++i)
+    if (stepping(shots[i])) act.push_back(shots[i]);
+  if (act.empty()) return DGRTM_OK;
+  dgrtm_mesh m = act[0]->mesh;
+  const int nl = act[0]->n_local;
+  for (auto *sh : act)
+    if ((s = pre_global(sh))) return s;
+  std::vector<int> modes(act.size());
+  std::vector<bool> rev(act.size());
+  std::vector<Field *> fld(act.size());
+  for (int ln = 0; ln < nl; ++ln) {
+    for (int md = 0; md < 3; ++md)
+      for (int prec = 0; prec < 2; ++prec) {
+        std::vector<size_t> grp;
+        for (size_t i = 0; i < act.size(); ++i) {
+          int mode;
+          bool r;
+          Field *f;
+          (void)phase_slot(act[i], mode, r, f);
+          if (mode == md && act[i]->args.precision == prec) grp.push_back(i);
+        }
+        for (size_t b = 0; b < grp.size(); b += kMaxSlots) {
+          const size_t e = std::min(grp.size(), b + kMaxSlots);
+          int mode;
+          bool r;
+          Field *f;
+          dgrtm_shot first = act[grp[b]];
+          (void)phase_slot(first, mode, r, f);
+          StepArgs a = mesh_args(m, prec, mode, r, nl);
+          a.nslots = (int)(e - b);
+          for (size_t i = b; i < e; ++i) {
+            dgrtm_shot sh = act[grp[i]];
+            a.slot[i - b] = phase_slot(sh, mode, r, f);
+            if (mode == MODE_IMAGE) a.slot[i - b].data_j = sh->n_global * nl - sh->R.tau;
+            fld[grp[i]] = f;
+          }
+          if ((s = launch_slots(first, a, ln))) return s;
+          for (size_t i = b; i < e; ++i) fld[grp[i]]->tau += 1;
+        }
+      }
+  }
+  for (auto *sh : act)
+    if ((s = post_global(sh))) return s;
+  return DGRTM_OK;
+}
+
 extern "C" dgrtm_status dgrtm_forward(dgrtm_shot sh, float *traces_out) {
   if (!sh) return fail(DGRTM_ERR_ARG, "dgrtm_forward: bad argument");
   dgrtm_mesh m = sh->mesh;
   dgrtm_status s;
-  if ((s = zero_field(sh, sh->S))) return s;
-  StepArgs a = base_args(sh, sh->S, false);
-  set_source(a, sh->src, 0);
-  a.wavelet = sh->wavelet;
-  if (!sh->args.has_source) a.eflag = m->eflag;
-  if ((s = record(sh, sh->S, 0))) return s;
-  for (int64_t g = 0; g < sh->n_global; ++g) {
-    if (g % sh->C == 0 && (s = ckpt_copy(sh, sh->S, g / sh->C, true))) return s;
-    for (int n = 0; n < sh->n_local; ++n)
-      if ((s = local_step(sh, sh->S, a))) return s;
-    if ((s = record(sh, sh->S, g + 1))) return s;
-  }
+  sh->full_rtm = false;
+  if ((s = begin_forward(sh))) return s;
+  while (sh->ph == DGRTM_PHASE_FORWARD)
+    if ((s = global_step_shots(&sh, 1))) return s;
   if (traces_out && sh->rec.n)
     HIPCHK(hipMemcpyAsync(traces_out, sh->traces, sh->rec.n * (sh->n_global + 1) * 4, hipMemcpyDeviceToDevice,
                           m->stream));
-  sh->forward_done = true;
+  return DGRTM_OK;
+}
+
+static dgrtm_status set_adjoint_params(dgrtm_shot sh, const float *data, int condition, const double *up,
+                                       int64_t g_image_start) {
+  if (!up) return fail(DGRTM_ERR_ARG, "adjoint: up vector missing");
+  if (condition != DGRTM_IMAGE_PRESSURE && condition != DGRTM_IMAGE_CHARACTERISTIC)
+    return fail(DGRTM_ERR_ARG, "adjoint: bad condition");
+  if (g_image_start < 0 || g_image_start >= sh->n_global) return fail(DGRTM_ERR_ARG, "adjoint: bad g_image_start");
+  sh->data = data;
+  sh->condition = condition;
+  for (int i = 0; i < 3; ++i) sh->up[i] = (float)up[i];
+  sh->g_image_start = g_image_start;
   return DGRTM_OK;
 }
 
 extern "C" dgrtm_status dgrtm_adjoint(dgrtm_shot sh, const float *data, int condition, const double *up,
                                       int64_t g_image_start) {
-  if (!sh || (sh->rec.n && !data) || !up) return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: bad argument");
+  if (!sh || (sh->rec.n && !data)) return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: bad argument");
   if (!sh->forward_done) return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: run dgrtm_forward first");
-  if (condition != DGRTM_IMAGE_PRESSURE && condition != DGRTM_IMAGE_CHARACTERISTIC)
-    return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: bad condition");
-  if (g_image_start < 0 || g_image_start >= sh->n_global) return fail(DGRTM_ERR_ARG, "dgrtm_adjoint: bad g_image_start");
-  dgrtm_mesh m = sh->mesh;
-  const HostMesh &h = m->hm;
-  const int Np = m->ref.Np;
-  const int64_t K = h.Ktot, NG = sh->n_global, NL = sh->n_local, C = sh->C;
   dgrtm_status s;
-  HIPCHK(launch_fill_f64(sh->img, (int64_t)Np * K, 0.0, m->stream));
-  if ((s = zero_field(sh, sh->R))) return s;
-  const float upf[3] = {(float)up[0], (float)up[1], (float)up[2]};
+  if ((s = set_adjoint_params(sh, data, condition, up, g_image_start))) return s;
+  if ((s = begin_adjoint(sh))) return s;
+  while (sh->ph != DGRTM_PHASE_DONE)
+    if ((s = global_step_shots(&sh, 1))) return s;
+  return DGRTM_OK;
+}
 
-  StepArgs as = base_args(sh, sh->S, false);
-  set_source(as, sh->src, 0);
-  as.wavelet = sh->wavelet;
-  if (!sh->args.has_source) as.eflag = m->eflag;
-  as.seg_q = sh->seg_q;
-  as.seg_r = sh->seg_r;
-  as.condition = condition;
-  std::memcpy(as.up, upf, sizeof(upf));
+extern "C" dgrtm_status dgrtm_shot_begin(dgrtm_shot sh, const float *data, int condition, const double *up,
+                                         int64_t g_image_start) {
+  if (!sh) return fail(DGRTM_ERR_ARG, "dgrtm_shot_begin: bad argument");
+  dgrtm_status s;
+  if ((s = set_adjoint_params(sh, data, condition, up, g_image_start))) return s;
+  sh->full_rtm = true;
+  return begin_forward(sh);
+}
 
-  StepArgs ar = base_args(sh, sh->R, true);
-  set_source(ar, sh->rec, 1);
-  if (!sh->rec.n) ar.eflag = m->eflag;
-  ar.data = data;
-  ar.n_t = NG + 1;
-  ar.src_scale = -1.0f;
-  ar.seg_q = sh->seg_q;
-  ar.seg_r = sh->seg_r;
-  ar.img = sh->img;
-  ar.condition = condition;
-  std::memcpy(ar.up, upf, sizeof(upf));
-  ar.image_from = g_image_start * NL;
-  for (int l = 1; l <= h.L; ++l) {
-    as.seg_q_off[l - 1] = ar.seg_q_off[l - 1] = sh->seg_q_off[l - 1];
-    as.seg_r_off[l - 1] = ar.seg_r_off[l - 1] = sh->seg_r_off[l - 1];
-    ar.own_total[l - 1] = NG << (l - 1);
+extern "C" dgrtm_status dgrtm_step_shots(dgrtm_shot *shots, int n, int64_t n_global) {
+  if (!shots || n < 0 || n_global < 0) return fail(DGRTM_ERR_ARG, "dgrtm_step_shots: bad argument");
+  for (int i = 0; i < n; ++i) {
+    if (!shots[i]) return fail(DGRTM_ERR_ARG, "dgrtm_step_shots: null shot");
+    if (shots[i]->mesh != shots[0]->mesh) return fail(DGRTM_ERR_ARG, "dgrtm_step_shots: shots on different meshes");
   }
-  for (int64_t c = (NG - 1) / C; c >= g_image_start / C; --c) {
+  dgrtm_status s;
+  for (int64_t k = 0; k < n_global; ++k)
+    if ((s = global_step_shots(shots, n))) return s;
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_shot_traces(dgrtm_shot sh, float *out) {
+  if (!sh || !out) return fail(DGRTM_ERR_ARG, "dgrtm_shot_traces: bad argument");
+  if (sh->rec.n)
+    HIPCHK(hipMemcpyAsync(out, sh->traces, sh->rec.n * (sh->n_global + 1) * 4, hipMemcpyDeviceToDevice,
+                          sh->mesh->stream));
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_shot_state(dgrtm_shot sh, int *phase, int64_t *steps_done, int64_t *steps_total) {
+  if (!sh) return fail(DGRTM_ERR_ARG, "dgrtm_shot_state: bad argument");
+  const int64_t NG = sh->n_global, C = sh->C;
+  // forward NG, then per segment (recompute + backward)
+  int64_t total = NG, done = 0;
+  for (int64_t c = (NG - 1) / C; c >= sh->g_image_start / C; --c) {
     const int64_t g0 = c * C, g1 = std::min(NG, g0 + C);
-    // restore S at g0 and recompute it over [g0, g1), recording q-_S and r-_S per element-step
-    if ((s = ckpt_copy(sh, sh->S, c, false))) return s;
-    sh->S.tau = g0 * NL;
-    if ((s = trace_init(sh, sh->S))) return s;
-    SegInitArgs si;
-    std::memset(&si, 0, sizeof(si));
-    si.ring = sh->S.ring;
-    si.geo = m->geo;
-    si.eflag = m->eflag;
-    si.seg_r = sh->seg_r;
-    si.Ktot = K;
-    si.L = h.L;
-    fill_level_begin(h, si.lev_begin);
-    std::memcpy(si.up, upf, sizeof(upf));
-    si.condition = condition;
-    for (int l = 1; l <= h.L; ++l) {
-      si.seg_r_off[l - 1] = sh->seg_r_off[l - 1];
-      si.seg_m0[l - 1] = as.seg_m0[l - 1] = ar.seg_m0[l - 1] = g0 << (l - 1);
-      as.seg_len[l - 1] = ar.seg_len[l - 1] = (g1 - g0) << (l - 1);
-    }
-    HIPCHK(launch_seg_init(m->ref.N, si, m->stream));
-    for (int64_t g = g0; g < g1; ++g)
-      for (int n = 0; n < NL; ++n)
-        if ((s = local_step(sh, sh->S, as))) return s;
-    // R backward over the same time span, imaging as it goes
-    const int64_t gr0 = NG - g1, gr1 = NG - std::max(g0, g_image_start);
-    for (int64_t gr = gr0; gr < gr1; ++gr)
-      for (int n = 0; n < NL; ++n) {
-        ar.data_j = NG * NL - sh->R.tau;
-        if ((s = local_step(sh, sh->R, ar))) return s;
-      }
+    total += (g1 - g0) + (g1 - std::max(g0, sh->g_image_start));
   }
+  switch (sh->ph) {
+    case DGRTM_PHASE_FORWARD: done = sh->g; break;
+    case DGRTM_PHASE_IDLE: done = sh->forward_done ? NG : 0; break;
+    case DGRTM_PHASE_DONE: done = total; break;
+    default: {
+      done = NG;
+      for (int64_t c = (NG - 1) / C; c > sh->c; --c) {
+        const int64_t g0 = c * C, g1 = std::min(NG, g0 + C);
+        done += (g1 - g0) + (g1 - std::max(g0, sh->g_image_start));
+      }
+      done += (sh->g - sh->g0) + (sh->gr - (NG - sh->g1));
+    }
+  }
+  if (phase) *phase = sh->ph;
+  if (steps_done) *steps_done = done;
+  if (steps_total) *steps_total = total;
   return DGRTM_OK;
 }
 
@@ -814,9 +1002,11 @@ extern "C" dgrtm_status dgrtm_apply_rhs(dgrtm_shot sh, const float *q, float *rh
   if ((s = zero_field(sh, sh->S))) return s;
   HIPCHK(launch_to_device_layout(Np, 4, q, sh->S.q, m->s2u, K, m->stream));
   if ((s = trace_init(sh, sh->S))) return s;
-  StepArgs a = base_args(sh, sh->S, reversed != 0);
-  a.rhs_out = sh->S.ring;
-  a.tau = 0;
+  StepArgs a = mesh_args(m, sh->args.precision, MODE_RHS_ONLY, reversed != 0, sh->n_local);
+  a.nslots = 1;
+  a.slot[0] = field_slot(sh, sh->S);
+  a.slot[0].rhs_out = sh->S.ring;
+  a.slot[0].tau = 0;
   a.k_end = K;
   HIPCHK(launch_step(m->ref.N, a, m->stream));
   HIPCHK(launch_to_user_layout(Np, 4, sh->S.ring, rhs, m->s2u, K, m->stream));
@@ -854,17 +1044,22 @@ extern "C" dgrtm_status dgrtm_run(dgrtm_shot sh, int which, int64_t n_global, in
   if (!sh || n_global < 0 || (which != 0 && which != 1)) return fail(DGRTM_ERR_ARG, "dgrtm_run: bad argument");
   dgrtm_mesh m = sh->mesh;
   Field &f = which ? sh->R : sh->S;
-  StepArgs a = base_args(sh, f, reversed != 0);
+  StepArgs a = mesh_args(m, sh->args.precision, MODE_PLAIN, reversed != 0, sh->n_local);
+  a.nslots = 1;
+  a.slot[0] = field_slot(sh, f);
   if (with_source && which == 0 && sh->args.has_source) {
-    set_source(a, sh->src, 0);
-    a.wavelet = sh->wavelet;
+    with_points(a.slot[0], sh->src, 0);
+    a.slot[0].wavelet = sh->wavelet;
     if (f.tau + n_global * sh->n_local > sh->n_global * sh->n_local)
       return fail(DGRTM_ERR_ARG, "dgrtm_run: source signal shorter than the run");
   }
   dgrtm_status s;
   for (int64_t g = 0; g < n_global; ++g)
-    for (int n = 0; n < sh->n_local; ++n)
-      if ((s = local_step(sh, f, a))) return s;
+    for (int n = 0; n < sh->n_local; ++n) {
+      a.slot[0].tau = f.tau;
+      if ((s = launch_slots(sh, a, f.tau))) return s;
+      f.tau += 1;
+    }
   HIPCHK(hipStreamSynchronize(m->stream));
   return DGRTM_OK;
 }

@@ -112,7 +112,7 @@ struct FaceCtx {
 };
 
 template <int N>
-__device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, int f, int64_t k, const float *gg) {
+__device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, const SlotArgs &sl, int f, int64_t k, const float *gg) {
   constexpr int Nfp = Dims<N>::Nfp, F = Dims<N>::F;
   const int64_t K = a.Ktot;
   FaceCtx c;
@@ -128,7 +128,7 @@ __device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, int f, int64_t k,
   const int code = a.ncode[f * K + k];
   c.taup = a.tau_sign * gg[12 + f];
   c.tauv = a.tau_sign * gg[16 + f];
-  c.trp = a.tr;
+  c.trp = sl.tr;
   c.tab = a.nbr_index;
   c.f2 = 0;
   if (c.nb >= 0) {
@@ -136,8 +136,8 @@ __device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, int f, int64_t k,
     const int perm = (code >> 2) & 7;
     const int shn = a.L - (code >> 5);
     // neighbour on its own step grid -> parity slot, otherwise (one level coarser) its mid step
-    const int slot = ((a.tau & ((1LL << shn) - 1)) == 0) ? (int)((a.tau >> shn) & 1) : 2;
-    c.trp = a.tr + (int64_t)slot * 2 * F * K;
+    const int slot = ((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2;
+    c.trp = sl.tr + (int64_t)slot * 2 * F * K;
     c.tab = a.nbr_index + ((f * 4 + c.f2) * 6 + perm) * Nfp;
   }
   return c;
@@ -146,13 +146,13 @@ __device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, int f, int64_t k,
 // Penalty terms at face node s (volume node `node`) of the lane's element, already scaled by
 // J_f/J: returns -P^p and the scalar part of P^v (P^{v_i} = n_i * Pv).
 template <int N>
-__device__ __forceinline__ void penalty(const StepArgs &a, const FaceCtx &c, int s, int node, int64_t k, float rc2,
-                                        float irho, float &mPp, float &Pv) {
+__device__ __forceinline__ void penalty(const StepArgs &a, const float *q, const FaceCtx &c, int s, int node, int64_t k,
+                                        float rc2, float irho, float &mPp, float &Pv) {
   constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F;
   const int64_t K = a.Ktot;
-  const float pm = a.q[(int64_t)node * K + k];
-  const float nvm = c.nx * a.q[(int64_t)(Np + node) * K + k] + c.ny * a.q[(int64_t)(2 * Np + node) * K + k] +
-                    c.nz * a.q[(int64_t)(3 * Np + node) * K + k];
+  const float pm = q[(int64_t)node * K + k];
+  const float nvm = c.nx * q[(int64_t)(Np + node) * K + k] + c.ny * q[(int64_t)(2 * Np + node) * K + k] +
+                    c.nz * q[(int64_t)(3 * Np + node) * K + k];
   float pp, nvp;
   if (c.nb >= 0) {
     const int64_t row = c.f2 * Nfp + c.tab[s];
@@ -176,8 +176,21 @@ __device__ __forceinline__ void penalty(const StepArgs &a, const FaceCtx &c, int
 // Everything after the operator products, in the MFMA C layout (lane: element e, rows
 // 16 rt + 4 g + i): point sources, output of a bare rhs, AB3 update, rhs ring, traces of the new
 // state and of the half step, source-wavefield segment record and FP64 image accumulation.
+// offsets of level `lev` in a slot's segment buffer (levels stored finest first, like the elements)
+__device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np, int lev, int64_t &oq, int64_t &orr) {
+  oq = 0;
+  orr = 0;
+  for (int l = 1; l < lev; ++l) {
+    const int64_t P = level_end(a.lev_begin, a.L, l) - a.lev_begin[l - 1];
+    const int64_t nst = C << (l - 1);
+    oq += nst * Np * P;
+    orr += (nst + 2) * Np * P;
+  }
+}
+
 template <int N, int MODE>
-__device__ __forceinline__ void tile_tail(const StepArgs &a, int64_t k, int g, int lev, int sh, int64_t m, int flag,
+__device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
+                                          int64_t m, int flag,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
                                           v4f (&rp)[Dims<N>::NR], v4f (&rvx)[Dims<N>::NR], v4f (&rvy)[Dims<N>::NR],
                                           v4f (&rvz)[Dims<N>::NR]) {
@@ -193,17 +206,17 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, int64_t k, int g, i
   }
   // ---- point sources (projected delta into the pressure equation)
   if (valid && (flag & 4)) {
-    const int s0 = a.src_start[k], scn = a.src_count[k];
+    const int s0 = sl.src_start[k], scn = sl.src_count[k];
     for (int en = s0; en < s0 + scn; ++en) {
-      const int pt = a.src_point[en];
+      const int pt = sl.src_point[en];
       float amp = 0.0f;
-      if (a.amp_mode == 0) {
-        amp = a.wavelet[a.tau];
+      if (sl.amp_mode == 0) {
+        amp = sl.wavelet[sl.tau];
       } else {
-        const int64_t j = a.data_j;
+        const int64_t j = sl.data_j;
         const int64_t gq = j / a.n_local, rem = j % a.n_local;
-        if (j >= 0 && (gq < a.n_t - 1 || (gq == a.n_t - 1 && rem == 0))) {
-          const float *d = a.data + (int64_t)pt * a.n_t;
+        if (j >= 0 && (gq < sl.n_t - 1 || (gq == sl.n_t - 1 && rem == 0))) {
+          const float *d = sl.data + (int64_t)pt * sl.n_t;
           if (rem == 0) amp = d[gq];
           else {
             const float th = (float)rem / (float)a.n_local;
@@ -211,8 +224,8 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, int64_t k, int g, i
           }
         }
       }
-      amp *= a.src_scale;
-      const float *w = a.src_w + (int64_t)pt * Np;
+      amp *= sl.src_scale;
+      const float *w = sl.src_w + (int64_t)pt * Np;
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt)
 #pragma unroll
@@ -230,36 +243,37 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, int64_t k, int g, i
       for (int i = 0; i < 4; ++i) {
         const int n = 16 * rt + 4 * g + i;
         if (16 * rt + 15 < Np || n < Np) {
-          a.rhs_out[(int64_t)(0 * Np + n) * K + k] = rp[rt][i];
-          a.rhs_out[(int64_t)(1 * Np + n) * K + k] = rvx[rt][i];
-          a.rhs_out[(int64_t)(2 * Np + n) * K + k] = rvy[rt][i];
-          a.rhs_out[(int64_t)(3 * Np + n) * K + k] = rvz[rt][i];
+          sl.rhs_out[(int64_t)(0 * Np + n) * K + k] = rp[rt][i];
+          sl.rhs_out[(int64_t)(1 * Np + n) * K + k] = rvx[rt][i];
+          sl.rhs_out[(int64_t)(2 * Np + n) * K + k] = rvy[rt][i];
+          sl.rhs_out[(int64_t)(3 * Np + n) * K + k] = rvz[rt][i];
         }
       }
     return;
   }
   const int64_t slab = (int64_t)4 * Np * K;
   const float dtl = (float)(a.dt_local * (double)(1LL << sh));
-  float *__restrict__ R0 = a.ring + (m % 3) * slab;
-  const float *__restrict__ R1 = a.ring + ((m + 2) % 3) * slab;
-  const float *__restrict__ R2 = a.ring + ((m + 1) % 3) * slab;
-  float *__restrict__ trw = a.tr + ((m + 1) & 1) * (int64_t)2 * F * K;
-  float *__restrict__ trm = a.tr + (int64_t)2 * 2 * F * K;
+  float *__restrict__ R0 = sl.ring + (m % 3) * slab;
+  const float *__restrict__ R1 = sl.ring + ((m + 2) % 3) * slab;
+  const float *__restrict__ R2 = sl.ring + ((m + 1) % 3) * slab;
+  float *__restrict__ trw = sl.tr + ((m + 1) & 1) * (int64_t)2 * F * K;
+  float *__restrict__ trm = sl.tr + (int64_t)2 * 2 * F * K;
   const bool mid = (flag & 2) != 0;
-  float *q = a.q;
-  const float ux = a.up[0], uy = a.up[1], uz = a.up[2];
-  const float zs = a.condition ? Z : 0.0f;
-  int64_t kk = 0, Pl = 0, jS = 0;
+  float *q = sl.q;
+  const float ux = sl.up[0], uy = sl.up[1], uz = sl.up[2];
+  const float zs = sl.condition ? Z : 0.0f;
+  int64_t kk = 0, Pl = 0, jS = 0, oq = 0, orr = 0;
   bool do_img = false;
   if constexpr (MODE == MODE_RECORD_SEG || MODE == MODE_IMAGE) {
     kk = k - a.lev_begin[lev - 1];
     Pl = level_end(a.lev_begin, a.L, lev) - a.lev_begin[lev - 1];
+    seg_offsets(a, sl.C, Np, lev, oq, orr);
   }
-  if constexpr (MODE == MODE_RECORD_SEG) jS = m - a.seg_m0[lev - 1];
+  if constexpr (MODE == MODE_RECORD_SEG) jS = m - (sl.g0 << (lev - 1));
   if constexpr (MODE == MODE_IMAGE) {
-    const int64_t mS = a.own_total[lev - 1] - m - 1;  // source step [t_a, t_b] of this receiver step
-    jS = mS - a.seg_m0[lev - 1];
-    do_img = (mS << sh) >= a.image_from && jS >= 0 && jS < a.seg_len[lev - 1];
+    const int64_t mS = (sl.NG << (lev - 1)) - m - 1;  // source step [t_a, t_b] of this receiver step
+    jS = mS - (sl.g0 << (lev - 1));
+    do_img = (mS << sh) >= sl.image_from && jS >= 0 && jS < ((sl.g1 - sl.g0) << (lev - 1));
   }
   const double dtd = a.dt_local * (double)(1LL << sh);
 
@@ -285,13 +299,13 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, int64_t k, int g, i
       if constexpr (MODE == MODE_RECORD_SEG) {
         const float qminus = qo[0] - zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
         const float rminus = r[0] - zs * (ux * r[1] + uy * r[2] + uz * r[3]);
-        a.seg_q[a.seg_q_off[lev - 1] + (jS * Np + n) * Pl + kk] = qminus;
-        a.seg_r[a.seg_r_off[lev - 1] + ((jS + 2) * Np + n) * Pl + kk] = rminus;
+        sl.seg_q[oq + (jS * Np + n) * Pl + kk] = qminus;
+        sl.seg_r[orr + ((jS + 2) * Np + n) * Pl + kk] = rminus;
       }
       if constexpr (MODE == MODE_IMAGE) {
         if (do_img) {
-          const float *sq = a.seg_q + a.seg_q_off[lev - 1];
-          const float *sr = a.seg_r + a.seg_r_off[lev - 1];
+          const float *sq = sl.seg_q + oq;
+          const float *sr = sl.seg_r + orr;
           const double qS = sq[(jS * Np + n) * Pl + kk];
           const double rS[3] = {sr[((jS + 2) * Np + n) * Pl + kk], sr[((jS + 1) * Np + n) * Pl + kk],
                                 sr[(jS * Np + n) * Pl + kk]};
@@ -306,7 +320,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, int64_t k, int g, i
           for (int s1 = 0; s1 < 3; ++s1)
 #pragma unroll
             for (int s2 = 0; s2 < 3; ++s2) inc3 += kCm[s1][s2] * rS[s1] * rR[s2];
-          a.img[(int64_t)n * K + k] += dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
+          sl.img[(int64_t)n * K + k] += dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
         }
       }
 #pragma unroll
@@ -369,6 +383,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
   const int e = lane & 15, g = lane >> 4;
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
+  const SlotArgs &sl = a.slot[blockIdx.y];
 
   for (int64_t grp = blockIdx.x; grp * 4 < ntiles; grp += gridDim.x) {
     const int64_t tile = grp * 4 + wave;
@@ -380,10 +395,10 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
     asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
     const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
     const float *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;    // [NR][4*FC][64]
-    const int flag = a.eflag[k];
+    const int flag = sl.eflag[k];
     const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
     const int sh = a.L - lev;
-    const int64_t m = a.tau >> sh;
+    const int64_t m = sl.tau >> sh;
 
     float gg[kGeo];
 #pragma unroll
@@ -401,10 +416,10 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
       const int mm = 4 * c + g;
       float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
       if (mm < Np) {
-        p = a.q[(int64_t)mm * K + k];
-        vx = a.q[(int64_t)(Np + mm) * K + k];
-        vy = a.q[(int64_t)(2 * Np + mm) * K + k];
-        vz = a.q[(int64_t)(3 * Np + mm) * K + k];
+        p = sl.q[(int64_t)mm * K + k];
+        vx = sl.q[(int64_t)(Np + mm) * K + k];
+        vy = sl.q[(int64_t)(2 * Np + mm) * K + k];
+        vz = sl.q[(int64_t)(3 * Np + mm) * K + k];
       }
       const float Ur = rx * vx + ry * vy + rz * vz;
       const float Us = sx * vx + sy * vy + sz * vz;
@@ -429,7 +444,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
     float nfx[4], nfy[4], nfz[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const FaceCtx fc = face_ctx<N>(a, f, k, gg);
+      const FaceCtx fc = face_ctx<N>(a, sl, f, k, gg);
       nfx[f] = fc.nx; nfy[f] = fc.ny; nfz[f] = fc.nz;
       v4f G[NR];
 #pragma unroll
@@ -441,7 +456,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
         if (4 * cc + 3 < Nfp || s < Nfp) {
           const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
                                 T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
-          penalty<N>(a, fc, s, node, k, rc2, irho, mPp, Pv);
+          penalty<N>(a, sl.q, fc, s, node, k, rc2, irho, mPp, Pv);
         }
 #pragma unroll
         for (int rt = 0; rt < NR; ++rt) {
@@ -460,7 +475,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE>(a, k, g, lev, sh, m, flag, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
   }
 }
 
@@ -493,6 +508,7 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
   const int e = lane & 15, g = lane >> 4;
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
+  const SlotArgs &sl = a.slot[blockIdx.y];
   auto hi = [](const uint4 &u) { return __builtin_bit_cast(v4s, uint2{u.x, u.y}); };
   auto lo = [](const uint4 &u) { return __builtin_bit_cast(v4s, uint2{u.z, u.w}); };
 
@@ -504,10 +520,10 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
     asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
     const uint4 *__restrict__ fD = ops + opaque0;                      // [3][NR][NK][64]
     const uint4 *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;   // [NR][4*FC][64]
-    const int flag = a.eflag[k];
+    const int flag = sl.eflag[k];
     const int lev = level_of(a.lev_begin, a.L, tile * 16);
     const int sh = a.L - lev;
-    const int64_t m = a.tau >> sh;
+    const int64_t m = sl.tau >> sh;
     float gg[kGeo];
 #pragma unroll
     for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[i * K + k];
@@ -526,10 +542,10 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
         const int mm = 16 * c + 4 * g + v;
         float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
         if (mm < Np) {
-          p = a.q[(int64_t)mm * K + k];
-          vx = a.q[(int64_t)(Np + mm) * K + k];
-          vy = a.q[(int64_t)(2 * Np + mm) * K + k];
-          vz = a.q[(int64_t)(3 * Np + mm) * K + k];
+          p = sl.q[(int64_t)mm * K + k];
+          vx = sl.q[(int64_t)(Np + mm) * K + k];
+          vy = sl.q[(int64_t)(2 * Np + mm) * K + k];
+          vz = sl.q[(int64_t)(3 * Np + mm) * K + k];
         }
         short h, l;
         split_bf16(rx * vx + ry * vy + rz * vz, h, l); urh[v] = h; url[v] = l;
@@ -557,7 +573,7 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
     float nfx[4], nfy[4], nfz[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const FaceCtx fc = face_ctx<N>(a, f, k, gg);
+      const FaceCtx fc = face_ctx<N>(a, sl, f, k, gg);
       nfx[f] = fc.nx; nfy[f] = fc.ny; nfz[f] = fc.nz;
       v4f G[NR];
 #pragma unroll
@@ -572,7 +588,7 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
           if (16 * cc + 12 + v < Nfp || s < Nfp) {
             const int node = sel4(g, T.fmask[f][min(16 * cc + v, Nfp - 1)], T.fmask[f][min(16 * cc + 4 + v, Nfp - 1)],
                                   T.fmask[f][min(16 * cc + 8 + v, Nfp - 1)], T.fmask[f][min(16 * cc + 12 + v, Nfp - 1)]);
-            penalty<N>(a, fc, s, node, k, rc2, irho, mPp, Pv);
+            penalty<N>(a, sl.q, fc, s, node, k, rc2, irho, mPp, Pv);
           }
           short h, l;
           split_bf16(mPp, h, l); pph[v] = h; ppl[v] = l;
@@ -596,7 +612,7 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE>(a, k, g, lev, sh, m, flag, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
   }
 }
 
@@ -744,7 +760,7 @@ template <int N, int MODE>
 static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
   const int64_t groups = (a.k_end / 16 + 3) / 4;
   const int64_t cap = a.max_groups > 0 ? a.max_groups : groups;
-  const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, cap))), block(256);
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, cap)), (unsigned)a.nslots), block(256);
   if (a.precision == 1) {
     constexpr size_t lds = (size_t)DimsB<N>::OPS_U4 * sizeof(uint4);
     if constexpr (lds <= 96 * 1024) {
@@ -771,11 +787,15 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
 
 template <int N>
 static hipError_t launch_step_n(const StepArgs &a, hipStream_t st) {
-  if (a.k_end <= 0) return hipSuccess;
-  if (a.rhs_out) return launch_step_mode<N, MODE_RHS_ONLY>(a, st);
-  if (a.img) return launch_step_mode<N, MODE_IMAGE>(a, st);
-  if (a.seg_q) return launch_step_mode<N, MODE_RECORD_SEG>(a, st);
-  return launch_step_mode<N, MODE_PLAIN>(a, st);
+  if (a.k_end <= 0 || a.nslots <= 0) return hipSuccess;
+  if (a.nslots > kMaxSlots) return hipErrorInvalidValue;
+  switch (a.mode) {
+    case MODE_RHS_ONLY: return launch_step_mode<N, MODE_RHS_ONLY>(a, st);
+    case MODE_IMAGE: return launch_step_mode<N, MODE_IMAGE>(a, st);
+    case MODE_RECORD_SEG: return launch_step_mode<N, MODE_RECORD_SEG>(a, st);
+    case MODE_PLAIN: return launch_step_mode<N, MODE_PLAIN>(a, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // operator fragments in the MFMA A-operand lane order (see step_kernel)

@@ -21,51 +21,58 @@ constexpr int kMaxLevels = 8;
 
 enum StepMode : int { MODE_PLAIN = 0, MODE_RECORD_SEG = 1, MODE_IMAGE = 2, MODE_RHS_ONLY = 3 };
 
+constexpr int kMaxSlots = 8;
+
+// Per-shot ("slot") part of a step launch: several shots on the same mesh, at the same phase of
+// their global step, share one launch (blockIdx.y selects the slot).
+struct SlotArgs {
+  float *q, *ring, *tr;
+  float *rhs_out;                     // MODE_RHS_ONLY output [4][Np][Ktot]
+  const int *eflag;                   // mesh flags | 4 on elements that hold this shot's points
+  // point sources: CSR per element (sorted position)
+  const int *src_start;               // [Ktot] first point entry
+  const int *src_count;               // [Ktot]
+  const int *src_point;               // entries -> point id
+  const float *src_w;                 // [n_points][Np] projected-delta weights
+  const float *wavelet;               // amp_mode 0: source signal at every local step
+  const float *data;                  // amp_mode 1: [n_points][n_t] samples at global steps
+  float *seg_q, *seg_r;               // segment buffer: per level [C N_l][Np][P_l] and [C N_l + 2][Np][P_l]
+  double *img;                        // [Np][Ktot]
+  int64_t tau;                        // local steps since the start of this field's run
+  int64_t n_t;
+  int64_t data_j;                     // physical time of this rhs in local steps (amp_mode 1)
+  int64_t C;                          // checkpoint interval (global steps)
+  int64_t g0, g1;                     // current segment [g0, g1) in global steps
+  int64_t NG;                         // global steps of the run
+  int64_t image_from;                 // image only where the source step starts at or after this local step
+  float up[3];
+  float src_scale;
+  int amp_mode;                       // 0 wavelet table, 1 linear data interpolation
+  int condition;                      // 0 pressure, 1 characteristic
+};
+
 struct StepArgs {
   // mesh
   const float *geo;
   const int *nbr;
   const int *ncode;
-  const int *eflag;
   const float *ops;                   // FP32 operator fragments (build_op_fragments)
   const uint32_t *ops_bf16;           // split-BF16 operator fragments (build_op_fragments_bf16)
-  int precision;                      // 0 FP32 MFMA, 1 split-BF16 MFMA
   const int8_t *nbr_index;            // [4][4][6][Nfp]
   int64_t Ktot;
   int L;                              // number of levels
   int64_t lev_begin[kMaxLevels + 1];  // index l-1 -> first position of level l (finest first)
-  // state
-  float *q, *ring, *tr;
-  float *rhs_out;                     // MODE_RHS_ONLY output [4][Np][Ktot]
-  // schedule
-  int64_t tau;                        // local steps since the start of the run
-  int64_t k_end;                      // active prefix (multiple of 64)
-  int64_t max_groups;                 // cap on work-groups (each takes 64 elements per pass); 0 = none
+  // launch
+  int64_t k_end;                      // active prefix (multiple of 64), the same for every slot
+  int64_t max_groups;                 // cap on work-groups along x; 0 = none
   double dt_local;
   float tau_sign;                     // +1 forward, -1 backward in time
   float out_sign;                     // +1 forward, -1 backward in time
-  // sources: CSR per element (sorted position)
-  const int *src_start;               // [Ktot] first point entry
-  const int *src_count;               // [Ktot]
-  const int *src_point;               // entries -> point id
-  const float *src_w;                 // [n_points][Np] projected-delta weights
-  int amp_mode;                       // 0: wavelet table per local step, 1: linear data interpolation
-  const float *wavelet;               // amp_mode 0: [n_steps] sampled source signal
-  const float *data;                  // amp_mode 1: [n_points][n_t]
-  int64_t n_t;
-  int64_t data_j;                     // physical time of this rhs in local steps (amp_mode 1)
   int n_local;                        // local steps per global step
-  float src_scale;
-  // segment buffer (S recompute) and image (R backward)
-  float *seg_q, *seg_r;               // per level: [n_seg_l][Np][P_l] and [n_seg_l+2][Np][P_l]
-  int64_t seg_q_off[kMaxLevels], seg_r_off[kMaxLevels];
-  int64_t seg_m0[kMaxLevels];         // first own step of the segment, per level
-  int64_t seg_len[kMaxLevels];        // own steps in the segment, per level
-  int64_t own_total[kMaxLevels];      // own steps of the whole run, per level (image mode)
-  int64_t image_from;                 // image only where the S step starts at or after this local step
-  double *img;                        // [Np][Ktot]
-  float up[3];
-  int condition;                      // 0 pressure, 1 characteristic
+  int precision;                      // 0 FP32 MFMA, 1 split-BF16 MFMA
+  int mode;                           // StepMode
+  int nslots;
+  SlotArgs slot[kMaxSlots];
 };
 
 hipError_t launch_step(int N, const StepArgs &a, hipStream_t st);

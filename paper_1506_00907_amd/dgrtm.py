@@ -19,6 +19,7 @@ BC_RIGID, BC_TRANSPARENT, BC_FREE = 1, 2, 3
 IMAGE_PRESSURE, IMAGE_CHARACTERISTIC = 0, 1
 FP32, SPLIT_BF16 = 0, 1
 SOURCE_FIELD, RECEIVER_FIELD = 0, 1
+PHASE_IDLE, PHASE_FORWARD, PHASE_RECOMPUTE, PHASE_BACKWARD, PHASE_DONE = 0, 1, 2, 3, 4
 
 _SYMBOLS = {
     "dgrtm_last_error": (C.c_char_p, []),
@@ -44,6 +45,10 @@ _SYMBOLS = {
     "dgrtm_set_state": (C.c_int32, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dgrtm_get_state": (C.c_int32, [C.c_void_p, C.c_int, C.c_void_p]),
     "dgrtm_run": (C.c_int32, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_int]),
+    "dgrtm_shot_begin": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
+    "dgrtm_step_shots": (C.c_int32, [C.c_void_p, C.c_int, C.c_int64]),
+    "dgrtm_shot_traces": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "dgrtm_shot_state": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "dgrtm_profile_start": (C.c_int32, [C.c_void_p, C.c_int]),
     "dgrtm_profile_read": (C.c_int32, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64)]),
@@ -264,6 +269,25 @@ class Shot:
     def run(self, which: int, n_global: int, reversed_time: bool = False, with_source: bool = False):
         _check(_lib.dgrtm_run(self.h, int(which), int(n_global), int(reversed_time), int(with_source)), "dgrtm_run")
 
+    # ---- pipeline (continuous batching)
+    def begin(self, data=None, condition: int = IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start: int = 0):
+        self._up = np.ascontiguousarray(up, dtype=np.float64)
+        self._data = data
+        _check(_lib.dgrtm_shot_begin(self.h, None if data is None else data.data_ptr(), int(condition),
+                                     _ptr(self._up), int(g_image_start)), "dgrtm_shot_begin")
+
+    def state(self):
+        ph, done, total = C.c_int(), C.c_int64(), C.c_int64()
+        _check(_lib.dgrtm_shot_state(self.h, C.byref(ph), C.byref(done), C.byref(total)), "dgrtm_shot_state")
+        return ph.value, done.value, total.value
+
+    def traces(self):
+        """The shot's own recorded traces (device copy)."""
+        torch = _torch()
+        out = torch.empty((self.n_rec, self.n_global + 1), dtype=torch.float32, device=self.mesh.device)
+        _check(_lib.dgrtm_shot_traces(self.h, out.data_ptr()), "dgrtm_shot_traces")
+        return out
+
     # ---- measurement
     def profile_start(self, sample_every: int):
         _check(_lib.dgrtm_profile_start(self.h, int(sample_every)), "dgrtm_profile_start")
@@ -278,3 +302,9 @@ class Shot:
         if getattr(self, "h", None):
             _lib.dgrtm_shot_destroy(self.h)
             self.h = None
+
+
+def step_shots(shots, n_global: int = 1):
+    """Advance several shots of one mesh by n_global global steps of their pipelines, batched."""
+    arr = (C.c_void_p * len(shots))(*[s.h for s in shots])
+    _check(_lib.dgrtm_step_shots(arr, len(shots), int(n_global)), "dgrtm_step_shots")
