@@ -59,6 +59,9 @@ struct Dims {
   static constexpr int NK = (Np + 3) / 4;     // 4-column chunks of D_j
   static constexpr int FC = (Nfp + 3) / 4;    // 4-column chunks per face of LIFT
   static constexpr int OPS = (3 * NR * NK + NR * 4 * FC) * 64;   // operator fragment floats
+  static constexpr int QR = 4 * NK;                               // rows per field of an LDS q tile
+  static constexpr int QT = 4 * QR * 16;                          // floats of one wavefront's q tile
+  static constexpr int TABW = (4 * 4 * 6 * Nfp + 3) / 4;          // face-node map, in 32-bit words
 };
 
 // AB3 weights of the full step and of the half step, image weights for the mixed-direction
@@ -188,9 +191,9 @@ __device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np
   }
 }
 
-template <int N, int MODE>
+template <int N, int MODE, bool QLDS = false>
 __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
-                                          int64_t m, int flag,
+                                          int64_t m, int flag, const float *sq, int e,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
                                           v4f (&rp)[Dims<N>::NR], v4f (&rvx)[Dims<N>::NR], v4f (&rvy)[Dims<N>::NR],
                                           v4f (&rvz)[Dims<N>::NR]) {
@@ -290,7 +293,8 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         const int64_t idx = (int64_t)(c * Np + n) * K + k;
         h1[c] = R1[idx];
         h2[c] = R2[idx];
-        qo[c] = q[idx];
+        if constexpr (QLDS) qo[c] = sq[(c * Dims<N>::QR + n) * 16 + e];
+        else qo[c] = q[idx];
         R0[idx] = r[c];
         qn[c] = qo[c] + dtl * (kA0 * r[c] + kA1 * h1[c] + kA2 * h2[c]);
         q[idx] = qn[c];
@@ -338,7 +342,6 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
           }
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -367,8 +370,195 @@ __device__ __forceinline__ void volume_to_rhs(const float *gg, const v4f (&cp)[N
 // elements (lane l holds rows 4(l/16)+i, i=0..3, of element l%16).  All elementwise work
 // (geometric factors, penalties, AB3, traces, image) runs in that C layout: lane l handles the
 // element e = l%16 and, in row tile rt, the nodes n = 16 rt + 4 (l/16) + i.
+//
+// Memory-level parallelism: at the start of a tile every lane issues, in one batch, the loads of
+// its share of the tile's fields and of the neighbour traces it will need, so one memory latency is
+// paid per tile.  The fields are then copied into an LDS tile ([4][QR][16] floats per wavefront),
+// from which the surface terms read their own traces and the update reads q.
 template <int N, int MODE, bool OPS_LDS>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
+  constexpr Tab<N> T{};
+  using Dm = Dims<N>;
+  constexpr int Np = Dm::Np, Nfp = Dm::Nfp, F = Dm::F, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC, QR = Dm::QR;
+  extern __shared__ float smem[];
+  const float *ops = a.ops;
+  int8_t *stab = reinterpret_cast<int8_t *>(smem + (OPS_LDS ? Dm::OPS : 0));
+  float *qtiles = smem + (OPS_LDS ? Dm::OPS : 0) + Dm::TABW;
+  if constexpr (OPS_LDS) {
+    for (int i = threadIdx.x; i < Dm::OPS; i += blockDim.x) smem[i] = a.ops[i];
+    ops = smem;
+  }
+  for (int i = threadIdx.x; i < 4 * 4 * 6 * Nfp; i += blockDim.x) stab[i] = a.nbr_index[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = lane & 15, g = lane >> 4;
+  const int64_t K = a.Ktot;
+  const int64_t ntiles = a.k_end >> 4;
+  const SlotArgs &sl = a.slot[blockIdx.y];
+  float *sq = qtiles + wave * Dm::QT;
+
+  for (int64_t grp = blockIdx.x; grp * 4 < ntiles; grp += gridDim.x) {
+    const int64_t tile = grp * 4 + wave;
+    if (tile >= ntiles) continue;
+    const int64_t k = tile * 16 + e;
+    int opaque0;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
+    const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
+    const float *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;    // [NR][4*FC][64]
+    const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
+    const int sh = a.L - lev;
+    const int64_t m = sl.tau >> sh;
+
+    // ---- batch 1: element data and this lane's share of the tile's fields
+    const int flag = sl.eflag[k];
+    float gg[kGeo];
+#pragma unroll
+    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[i * K + k];
+    int nbv[4], codev[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      nbv[f] = a.nbr[f * K + k];
+      codev[f] = a.ncode[f * K + k];
+    }
+    float qv[NK][4];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+      const int mm = 4 * c + g;
+#pragma unroll
+      for (int fl = 0; fl < 4; ++fl) qv[c][fl] = (4 * c + 3 < Np || mm < Np) ? sl.q[(int64_t)(fl * Np + mm) * K + k] : 0.f;
+    }
+    // ---- batch 2: neighbour traces of every face node this lane handles
+    float ntp[4][FC], ntv[4][FC];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int nb = nbv[f], code = codev[f];
+      const int f2 = code & 3, perm = (code >> 2) & 7, shn = a.L - (code >> 5);
+      const int slot = nb >= 0 ? (((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2) : 0;
+      const float *trp = sl.tr + (int64_t)slot * 2 * F * K;
+      const int8_t *tab = stab + ((f * 4 + f2) * 6 + perm) * Nfp;
+#pragma unroll
+      for (int cc = 0; cc < FC; ++cc) {
+        const int s = 4 * cc + g;
+        ntp[f][cc] = 0.f;
+        ntv[f][cc] = 0.f;
+        if (nb >= 0 && (4 * cc + 3 < Nfp || s < Nfp)) {
+          const int64_t row = f2 * Nfp + tab[s];
+          ntp[f][cc] = trp[row * K + nb];
+          ntv[f][cc] = trp[(F + row) * K + nb];
+        }
+      }
+    }
+    // the tile's fields into LDS (own traces and the update read them from there)
+#pragma unroll
+    for (int c = 0; c < NK; ++c)
+#pragma unroll
+      for (int fl = 0; fl < 4; ++fl) sq[(fl * QR + 4 * c + g) * 16 + e] = qv[c][fl];
+
+    const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
+                tz = gg[8];
+    const float rc2 = gg[9], irho = gg[10];
+
+    // ---- volume: Cp = sum_j D_j U_j and W_j = D_j p
+    v4f cp[NR], w0[NR], w1[NR], w2[NR];
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+      const float p = qv[c][0], vx = qv[c][1], vy = qv[c][2], vz = qv[c][3];
+      const float Ur = rx * vx + ry * vy + rz * vz;
+      const float Us = sx * vx + sy * vy + sz * vz;
+      const float Ut = tx * vx + ty * vy + tz * vz;
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt) {
+        const float ar = fD[((0 * NR + rt) * NK + c) * 64 + lane];
+        const float as = fD[((1 * NR + rt) * NK + c) * 64 + lane];
+        const float at = fD[((2 * NR + rt) * NK + c) * 64 + lane];
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, Ur, cp[rt], 0, 0, 0);
+        w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, p, w0[rt], 0, 0, 0);
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, Us, cp[rt], 0, 0, 0);
+        w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, p, w1[rt], 0, 0, 0);
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Ut, cp[rt], 0, 0, 0);
+        w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, p, w2[rt], 0, 0, 0);
+      }
+    }
+    v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
+    volume_to_rhs<NR>(gg, cp, w0, w1, w2, rp, rvx, rvy, rvz);
+
+    // ---- surface: rp -= LIFT Pp (accumulated by the MFMA with -Pp), G_f = LIFT_f Pv, rv -= n_f G_f
+    float nfx[4], nfy[4], nfz[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      float nx, ny, nz;
+      if (f == 0) { nx = -tx; ny = -ty; nz = -tz; }
+      else if (f == 1) { nx = -sx; ny = -sy; nz = -sz; }
+      else if (f == 2) { nx = rx + sx + tx; ny = ry + sy + ty; nz = rz + sz + tz; }
+      else { nx = -rx; ny = -ry; nz = -rz; }
+      const float Fs = sqrtf(nx * nx + ny * ny + nz * nz);  // J_f / J
+      const float inv = 1.0f / Fs;
+      nx *= inv; ny *= inv; nz *= inv;
+      nfx[f] = nx; nfy[f] = ny; nfz[f] = nz;
+      const int nb = nbv[f];
+      const float taup = a.tau_sign * gg[12 + f], tauv = a.tau_sign * gg[16 + f];
+      v4f G[NR];
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int cc = 0; cc < FC; ++cc) {
+        const int s = 4 * cc + g;   // face node handled by this lane in this chunk
+        float mPp = 0.f, Pv = 0.f;
+        if (4 * cc + 3 < Nfp || s < Nfp) {
+          const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
+                                T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
+          const float pm = sq[(0 * QR + node) * 16 + e];
+          const float nvm = nx * sq[(1 * QR + node) * 16 + e] + ny * sq[(2 * QR + node) * 16 + e] +
+                            nz * sq[(3 * QR + node) * 16 + e];
+          float pp, nvp;
+          if (nb >= 0) {
+            pp = ntp[f][cc];
+            nvp = -ntv[f][cc];  // n- . v+ = -(n+ . v+)
+          } else if (nb == -1) {  // rigid wall
+            pp = pm;
+            nvp = -nvm;
+          } else if (nb == -2) {  // transparent
+            pp = 0.0f;
+            nvp = 0.0f;
+          } else {  // free surface
+            pp = -pm;
+            nvp = nvm;
+          }
+          const float dp = pp - pm, dnv = nvp - nvm;
+          mPp = -0.5f * rc2 * (dnv - taup * dp) * Fs;
+          Pv = 0.5f * irho * (dp - tauv * dnv) * Fs;
+        }
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt) {
+          const float al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
+          rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
+          G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          rvx[rt][i] -= nx * G[rt][i];
+          rvy[rt][i] -= ny * G[rt][i];
+          rvz[rt][i] -= nz * G[rt][i];
+        }
+    }
+    tile_tail<N, MODE, true>(a, sl, k, g, lev, sh, m, flag, sq, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+  }
+}
+
+// Lower-register variant for N >= 5 (fields loaded chunk by chunk, no LDS tile), same layout as
+// step_kernel.  One wavefront owns a tile of 16 consecutive elements.  The element-batched operator products
+// run on v_mfma_f32_16x16x4_f32: A = 16 operator rows x 4 columns (lane l holds
+// A[l%16][l/16]), B = 4 input nodes x 16 elements (lane l holds B[l/16][l%16]), C = 16 rows x 16
+// elements (lane l holds rows 4(l/16)+i, i=0..3, of element l%16).  All elementwise work
+// (geometric factors, penalties, AB3, traces, image) runs in that C layout: lane l handles the
+// element e = l%16 and, in row tile rt, the nodes n = 16 rt + 4 (l/16) + i.
+template <int N, int MODE, bool OPS_LDS>
+__global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   constexpr Tab<N> T{};
   using Dm = Dims<N>;
   constexpr int Np = Dm::Np, Nfp = Dm::Nfp, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
@@ -475,7 +665,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, nullptr, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
   }
 }
 
@@ -612,7 +802,7 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, nullptr, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
   }
 }
 
@@ -773,14 +963,28 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
     }
     return hipGetLastError();
   }
-  constexpr size_t lds = Dims<N>::OPS * sizeof(float);
-  if constexpr (lds <= 96 * 1024) {
+  constexpr size_t extra = (Dims<N>::TABW + 4 * Dims<N>::QT) * sizeof(float);
+  constexpr size_t lds = Dims<N>::OPS * sizeof(float) + extra;
+  if constexpr (N >= 5) {
+    constexpr size_t lds_lr = Dims<N>::OPS * sizeof(float);
+    if constexpr (lds_lr <= 96 * 1024) {
+      static bool done = false;
+      hipError_t e = ensure_lds(step_kernel_lowreg<N, MODE, true>, lds_lr, done);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, true>), grid, block, lds_lr, st, a);
+    } else {
+      hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, false>), grid, block, 0, st, a);
+    }
+  } else if constexpr (lds <= 128 * 1024) {
     static bool done = false;
     hipError_t e = ensure_lds(step_kernel<N, MODE, true>, lds, done);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((step_kernel<N, MODE, true>), grid, block, lds, st, a);
   } else {
-    hipLaunchKernelGGL((step_kernel<N, MODE, false>), grid, block, 0, st, a);
+    static bool done = false;
+    hipError_t e = ensure_lds(step_kernel<N, MODE, false>, extra, done);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((step_kernel<N, MODE, false>), grid, block, extra, st, a);
   }
   return hipGetLastError();
 }
