@@ -158,9 +158,9 @@ __device__ __forceinline__ void penalty(const StepArgs &a, const float *q, const
                     c.nz * q[(int64_t)(3 * Np + node) * K + k];
   float pp, nvp;
   if (c.nb >= 0) {
-    const int64_t row = c.f2 * Nfp + c.tab[s];
-    pp = c.trp[row * K + c.nb];
-    nvp = -c.trp[(F + row) * K + c.nb];  // n- . v+ = -(n+ . v+)
+    const float *nbt = c.trp + (int64_t)c.nb * 2 * F + c.f2 * Nfp + c.tab[s];
+    pp = nbt[0];
+    nvp = -nbt[F];  // n- . v+ = -(n+ . v+)
   } else if (c.nb == -1) {  // rigid wall
     pp = pm;
     nvp = -nvm;
@@ -332,8 +332,8 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         const int fi = sel4(g, T.fidx[min(16 * rt + i, Np - 1)][f], T.fidx[min(16 * rt + 4 + i, Np - 1)][f],
                             T.fidx[min(16 * rt + 8 + i, Np - 1)][f], T.fidx[min(16 * rt + 12 + i, Np - 1)][f]);
         if (fi >= 0) {
-          const int64_t r0 = (int64_t)(f * Nfp + fi) * K + k;
-          const int64_t r1 = (int64_t)(F + f * Nfp + fi) * K + k;
+          const int64_t r0 = (int64_t)k * 2 * F + f * Nfp + fi;
+          const int64_t r1 = r0 + F;
           trw[r0] = qn[0];
           trw[r1] = nfx[f] * qn[1] + nfy[f] * qn[2] + nfz[f] * qn[3];
           if (mid) {
@@ -442,9 +442,9 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
         ntp[f][cc] = 0.f;
         ntv[f][cc] = 0.f;
         if (nb >= 0 && (4 * cc + 3 < Nfp || s < Nfp)) {
-          const int64_t row = f2 * Nfp + tab[s];
-          ntp[f][cc] = trp[row * K + nb];
-          ntv[f][cc] = trp[(F + row) * K + nb];
+          const float *nbt = trp + (int64_t)nb * 2 * F + f2 * Nfp + tab[s];
+          ntp[f][cc] = nbt[0];
+          ntv[f][cc] = nbt[F];
         }
       }
     }
@@ -836,8 +836,8 @@ __global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) 
       const float vx = a.q[(int64_t)(Np + node) * K + k];
       const float vy = a.q[(int64_t)(2 * Np + node) * K + k];
       const float vz = a.q[(int64_t)(3 * Np + node) * K + k];
-      tr[(int64_t)(f * Nfp + i) * K + k] = p;
-      tr[(int64_t)(F + f * Nfp + i) * K + k] = nx * vx + ny * vy + nz * vz;
+      tr[(int64_t)k * 2 * F + f * Nfp + i] = p;
+      tr[(int64_t)k * 2 * F + F + f * Nfp + i] = nx * vx + ny * vy + nz * vz;
     }
   }
 }

@@ -4,7 +4,7 @@
 // segment padded to a multiple of 64 so a wavefront never straddles two levels):
 //   q     [4][Np][Ktot]            p, vx, vy, vz
 //   ring  [3][4][Np][Ktot]         AB3 right-hand-side history, slot = own step index mod 3
-//   tr    [3][2][4*Nfp][Ktot]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step
+//   tr    [3][Ktot][2][4*Nfp]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step
 //   geo   [kGeo][Ktot]             rx ry rz sx sy sz tx ty tz, rho c^2, 1/rho, Z, tau_p[4], tau_v[4]
 //   nbr   [4][Ktot]                neighbour position, or -(boundary type) on a boundary face
 //   ncode [4][Ktot]                neighbour face | vertex permutation << 2 | neighbour level << 5
