@@ -96,6 +96,38 @@ def cpu_baseline(mesh_in, rho, c, N, n_levels, seconds_target=15.0):
                       f"on the same {om.K}-element mesh, {dt:.1f} s"}
 
 
+def serving_bench(n_requests=12, t_final=0.05, meshes=("srv_50k", "srv_200k", "srv_800k"), seed=7,
+                  hbm_budget=200 * 2 ** 30):
+    """Continuous batching vs the one-shot-at-a-time FP32 solve on the same seeded Poisson stream."""
+    import copy
+    import numpy as np
+    from paper_1506_00907_amd import serving as S
+    pools = {m: S.MeshSlotPool(m) for m in meshes}
+    # capacity of the sequential solver: one warm-up shot per mesh
+    svc = []
+    for m in meshes:
+        req = S.Request(-1, m, (1.0, 1.0), 15.0, 0.0, t_final)
+        pools[m].run_alone(req)                      # compile / first-touch
+        t0 = time.perf_counter()
+        pools[m].run_alone(req)
+        svc.append(time.perf_counter() - t0)
+    capacity = 1.0 / float(np.mean(svc))
+    rate = 1.2 * capacity
+    reqs = S.make_requests(n_requests, rate, list(meshes), t_final, seed=seed)
+    seq_res, bat_res = {}, {}
+    rs = S.serve_sequential(pools, copy.deepcopy(reqs), results=seq_res)
+    rb = S.serve_batched(pools, copy.deepcopy(reqs), hbm_budget, results=bat_res)
+    worst_img, worst_tr = 0.0, 0.0
+    for rid in seq_res:
+        (ta, ia), (tb, ib) = seq_res[rid], bat_res[rid]
+        worst_tr = max(worst_tr, float(np.abs(ta - tb).max() / max(np.abs(ta).max(), 1e-30)))
+        worst_img = max(worst_img, float(np.linalg.norm(ia - ib) / max(np.linalg.norm(ia), 1e-30)))
+    return {"requests": n_requests, "t_final_s": t_final, "meshes": list(meshes),
+            "arrival_rate_per_s": round(rate, 4), "sequential_capacity_per_s": round(capacity, 4),
+            "batched": rb.summary(), "sequential": rs.summary(),
+            "mix_vs_alone_max_rel_image_diff": worst_img, "mix_vs_alone_max_rel_trace_diff": worst_tr}
+
+
 def _threads() -> int:
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         if os.environ.get(k):
@@ -112,6 +144,8 @@ def main():
     ap.add_argument("--t-final", type=float, default=1.0)
     ap.add_argument("--sample-every", type=int, default=7, help="time every n-th step-kernel launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=0, help="requests in the serving section (0 = skip)")
+    ap.add_argument("--serving-t-final", type=float, default=0.05)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the whole mesh and shot live on one MI355X "
@@ -200,6 +234,9 @@ def main():
                      "frac": round(rl[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
                      "traffic": tr, "per_mode": rl},
     }
+    if args.serving > 0:
+        del shot, traces, img
+        out["serving"] = serving_bench(args.serving, args.serving_t_final)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mm, rho, c, N, n_levels)
     print(json.dumps(out), flush=True)
