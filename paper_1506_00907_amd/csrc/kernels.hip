@@ -280,43 +280,66 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
   }
   const double dtd = a.dt_local * (double)(1LL << sh);
 
+  // Row tile by row tile: every load of the tile (rhs history, q, segment data, image) is issued
+  // before any store, so the loads of one row tile are in flight together (stores to the ring could
+  // otherwise alias later ring loads and serialise every load behind the previous store).
 #pragma unroll
-  for (int rt = 0; rt < NR; ++rt)
+  for (int rt = 0; rt < NR; ++rt) {
+    float h1[4][4], h2[4][4], qo[4][4];
+    float sqv[4] = {0.f, 0.f, 0.f, 0.f}, srv[4][3] = {};
+    double imv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int n = 16 * rt + 4 * g + i;
+      const bool ok = (16 * rt + 15 < Np || n < Np);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t idx = (int64_t)(c * Np + (ok ? n : 0)) * K + k;
+        h1[i][c] = ok ? R1[idx] : 0.f;
+        h2[i][c] = ok ? R2[idx] : 0.f;
+        if constexpr (QLDS) qo[i][c] = sq[(c * Dims<N>::QR + (ok ? n : 0)) * 16 + e];
+        else qo[i][c] = ok ? q[idx] : 0.f;
+      }
+      if constexpr (MODE == MODE_IMAGE) {
+        if (do_img && ok) {
+          const float *sqp = sl.seg_q + oq;
+          const float *srp = sl.seg_r + orr;
+          sqv[i] = sqp[(jS * Np + n) * Pl + kk];
+          srv[i][0] = srp[((jS + 2) * Np + n) * Pl + kk];
+          srv[i][1] = srp[((jS + 1) * Np + n) * Pl + kk];
+          srv[i][2] = srp[(jS * Np + n) * Pl + kk];
+          imv[i] = sl.img[(int64_t)n * K + k];
+        }
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int n = 16 * rt + 4 * g + i;
       if (!(16 * rt + 15 < Np || n < Np)) continue;
       const float r[4] = {rp[rt][i], rvx[rt][i], rvy[rt][i], rvz[rt][i]};
-      float qo[4], h1[4], h2[4], qn[4], qm[4];
+      float qn[4], qm[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t idx = (int64_t)(c * Np + n) * K + k;
-        h1[c] = R1[idx];
-        h2[c] = R2[idx];
-        if constexpr (QLDS) qo[c] = sq[(c * Dims<N>::QR + n) * 16 + e];
-        else qo[c] = q[idx];
         R0[idx] = r[c];
-        qn[c] = qo[c] + dtl * (kA0 * r[c] + kA1 * h1[c] + kA2 * h2[c]);
+        qn[c] = qo[i][c] + dtl * (kA0 * r[c] + kA1 * h1[i][c] + kA2 * h2[i][c]);
         q[idx] = qn[c];
-        qm[c] = qo[c] + dtl * (kB0 * r[c] + kB1 * h1[c] + kB2 * h2[c]);
+        qm[c] = qo[i][c] + dtl * (kB0 * r[c] + kB1 * h1[i][c] + kB2 * h2[i][c]);
       }
       if constexpr (MODE == MODE_RECORD_SEG) {
-        const float qminus = qo[0] - zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
+        const float qminus = qo[i][0] - zs * (ux * qo[i][1] + uy * qo[i][2] + uz * qo[i][3]);
         const float rminus = r[0] - zs * (ux * r[1] + uy * r[2] + uz * r[3]);
         sl.seg_q[oq + (jS * Np + n) * Pl + kk] = qminus;
         sl.seg_r[orr + ((jS + 2) * Np + n) * Pl + kk] = rminus;
       }
       if constexpr (MODE == MODE_IMAGE) {
         if (do_img) {
-          const float *sq = sl.seg_q + oq;
-          const float *sr = sl.seg_r + orr;
-          const double qS = sq[(jS * Np + n) * Pl + kk];
-          const double rS[3] = {sr[((jS + 2) * Np + n) * Pl + kk], sr[((jS + 1) * Np + n) * Pl + kk],
-                                sr[(jS * Np + n) * Pl + kk]};
-          const double qR = qo[0] + zs * (ux * qo[1] + uy * qo[2] + uz * qo[3]);
+          const double qS = sqv[i];
+          const double rS[3] = {srv[i][0], srv[i][1], srv[i][2]};
+          const double qR = qo[i][0] + zs * (ux * qo[i][1] + uy * qo[i][2] + uz * qo[i][3]);
           const double rR[3] = {r[0] + zs * (ux * r[1] + uy * r[2] + uz * r[3]),
-                                h1[0] + zs * (ux * h1[1] + uy * h1[2] + uz * h1[3]),
-                                h2[0] + zs * (ux * h2[1] + uy * h2[2] + uz * h2[3])};
+                                h1[i][0] + zs * (ux * h1[i][1] + uy * h1[i][2] + uz * h1[i][3]),
+                                h2[i][0] + zs * (ux * h2[i][1] + uy * h2[i][2] + uz * h2[i][3])};
           double inc2 = 0.0, inc3 = 0.0;
 #pragma unroll
           for (int s = 0; s < 3; ++s) inc2 += kE[s] * (qS * rR[s] + rS[s] * qR);
@@ -324,7 +347,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
           for (int s1 = 0; s1 < 3; ++s1)
 #pragma unroll
             for (int s2 = 0; s2 < 3; ++s2) inc3 += kCm[s1][s2] * rS[s1] * rR[s2];
-          sl.img[(int64_t)n * K + k] += dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
+          sl.img[(int64_t)n * K + k] = imv[i] + dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
         }
       }
 #pragma unroll
@@ -343,6 +366,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         }
       }
     }
+  }
 }
 
 // converts the volume accumulators (sum_j D_j U_j and D_j p) into the pressure and velocity rhs
