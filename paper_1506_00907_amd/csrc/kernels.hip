@@ -74,6 +74,29 @@ constexpr double kCm[3][3] = {{3341.0 / 10080.0, -667.0 / 5040.0, 43.0 / 1120.0}
                               {-667.0 / 5040.0, 19.0 / 420.0, -13.0 / 1008.0},
                               {43.0 / 1120.0, -13.0 / 1008.0, 37.0 / 10080.0}};
 
+// Copy nwords 32-bit words from global to LDS with the whole work-group: all 16-byte loads of a
+// thread are issued before its LDS stores, so the copy costs one memory latency.
+template <int NWORDS>
+__device__ __forceinline__ void stage_to_lds(const void *src, void *dst) {
+  constexpr int NV = NWORDS / 4, PER = (NV + 255) / 256;
+  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+  uint4 buf[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    if (i < NV) buf[j] = s4[i];
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    if (i < NV) d4[i] = buf[j];
+  }
+  const uint32_t *s1 = reinterpret_cast<const uint32_t *>(src);
+  uint32_t *d1 = reinterpret_cast<uint32_t *>(dst);
+  for (int i = 4 * NV + threadIdx.x; i < NWORDS; i += 256) d1[i] = s1[i];
+}
+
 __device__ __forceinline__ int level_of(const int64_t *lev_begin, int L, int64_t k) {
   // segments are stored finest first, so starts decrease with the level number
   for (int l = 1; l < L; ++l)
@@ -409,10 +432,10 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
   int8_t *stab = reinterpret_cast<int8_t *>(smem + (OPS_LDS ? Dm::OPS : 0));
   float *qtiles = smem + (OPS_LDS ? Dm::OPS : 0) + Dm::TABW;
   if constexpr (OPS_LDS) {
-    for (int i = threadIdx.x; i < Dm::OPS; i += blockDim.x) smem[i] = a.ops[i];
+    stage_to_lds<Dm::OPS>(a.ops, smem);
     ops = smem;
   }
-  for (int i = threadIdx.x; i < 4 * 4 * 6 * Nfp; i += blockDim.x) stab[i] = a.nbr_index[i];
+  stage_to_lds<4 * 4 * 6 * Nfp / 4>(a.nbr_index, stab);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = lane & 15, g = lane >> 4;
@@ -589,7 +612,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   extern __shared__ float sops[];
   const float *ops = a.ops;
   if constexpr (OPS_LDS) {
-    for (int i = threadIdx.x; i < Dm::OPS; i += blockDim.x) sops[i] = a.ops[i];
+    stage_to_lds<Dm::OPS>(a.ops, sops);
     __syncthreads();
     ops = sops;
   }
@@ -714,7 +737,7 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
   extern __shared__ uint4 sopsb[];
   const uint4 *ops = reinterpret_cast<const uint4 *>(a.ops_bf16);
   if constexpr (OPS_LDS) {
-    for (int i = threadIdx.x; i < Dm::OPS_U4; i += blockDim.x) sopsb[i] = ops[i];
+    stage_to_lds<Dm::OPS_U4 * 4>(ops, sopsb);
     __syncthreads();
     ops = sopsb;
   }
@@ -970,10 +993,23 @@ static hipError_t ensure_lds(KernelFn fn, size_t lds, bool &done) {
   return hipSuccess;
 }
 
+static int64_t device_cus() {
+  static int64_t cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
 template <int N, int MODE>
 static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
   const int64_t groups = (a.k_end / 16 + 3) / 4;
-  const int64_t cap = a.max_groups > 0 ? a.max_groups : groups;
+  // a persistent-style grid: each work-group stages the operators once and then takes tile groups
+  const int64_t cap = a.max_groups > 0 ? a.max_groups : 2 * device_cus();
   const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, cap)), (unsigned)a.nslots), block(256);
   if (a.precision == 1) {
     constexpr size_t lds = (size_t)DimsB<N>::OPS_U4 * sizeof(uint4);
