@@ -359,7 +359,7 @@ static size_t shot_layout(dgrtm_shot sh, Bump &b) {
   for (Field *f : {&sh->S, &sh->R}) {
     f->q = b.take<float>((size_t)4 * Np * K);
     f->ring = b.take<float>((size_t)12 * Np * K);
-    f->tr = b.take<float>((size_t)6 * F * K);
+    f->tr = b.take<float>((size_t)3 * trace_row(m->ref.Nfp) * K);
   }
   sh->img = b.take<double>((size_t)Np * K);
   sh->ckpt = b.take<float>((size_t)sh->n_ckpt * 12 * Np * K);
@@ -580,7 +580,7 @@ static dgrtm_status zero_field(dgrtm_shot sh, Field &f) {
   const int64_t K = m->hm.Ktot;
   HIPCHK(launch_fill_f32(f.q, 4LL * Np * K, 0.0f, m->stream));
   HIPCHK(launch_fill_f32(f.ring, 12LL * Np * K, 0.0f, m->stream));
-  HIPCHK(launch_fill_f32(f.tr, 6LL * F * K, 0.0f, m->stream));
+  HIPCHK(launch_fill_f32(f.tr, 3LL * trace_row(m->ref.Nfp) * K, 0.0f, m->stream));
   f.tau = 0;
   return DGRTM_OK;
 }

@@ -2,10 +2,11 @@
 // local step (with optional source-wavefield recording and FP64 image accumulation), trace
 // initialisation, receiver sampling, layout conversion and FP64 reductions.
 //
-// One lane owns one element (64 elements per wavefront); all field arrays are node-major
-// with the element index fastest, so every load and store of q, the rhs ring and the trace
-// copies is coalesced across the wavefront.  The reference operators are the same for every
-// lane: their addresses are wavefront-uniform and are served by scalar loads.
+// A wavefront owns a tile of 16 consecutive elements; the operator products of the tile run on
+// the matrix cores with the 16 elements as the MFMA N dimension.  All field arrays are node-major
+// with the element index fastest, so a tile's share of any node row is 64 contiguous bytes.  The
+// reference operators are the same for every element and are staged once per work-group in LDS,
+// in the MFMA A-operand lane order.
 #include "kernels.hpp"
 
 #include <algorithm>
@@ -62,6 +63,9 @@ struct Dims {
   static constexpr int QR = 4 * NK;                               // rows per field of an LDS q tile
   static constexpr int QT = 4 * QR * 16;                          // floats of one wavefront's q tile
   static constexpr int TABW = (4 * 4 * 6 * Nfp + 3) / 4;          // face-node map, in 32-bit words
+  static constexpr int FS = trace_face_stride(Nfp);               // trace row: face stride,
+  static constexpr int TRC = 4 * FS;                              // component stride,
+  static constexpr int TRS = 2 * TRC;                             // element stride (floats)
 };
 
 // AB3 weights of the full step and of the half step, image weights for the mixed-direction
@@ -163,7 +167,7 @@ __device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, const SlotArgs &s
     const int shn = a.L - (code >> 5);
     // neighbour on its own step grid -> parity slot, otherwise (one level coarser) its mid step
     const int slot = ((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2;
-    c.trp = sl.tr + (int64_t)slot * 2 * F * K;
+    c.trp = sl.tr + (int64_t)slot * Dims<N>::TRS * K;
     c.tab = a.nbr_index + ((f * 4 + c.f2) * 6 + perm) * Nfp;
   }
   return c;
@@ -181,9 +185,9 @@ __device__ __forceinline__ void penalty(const StepArgs &a, const float *q, const
                     c.nz * q[(int64_t)(3 * Np + node) * K + k];
   float pp, nvp;
   if (c.nb >= 0) {
-    const float *nbt = c.trp + (int64_t)c.nb * 2 * F + c.f2 * Nfp + c.tab[s];
+    const float *nbt = c.trp + (int64_t)c.nb * Dims<N>::TRS + c.f2 * Dims<N>::FS + c.tab[s];
     pp = nbt[0];
-    nvp = -nbt[F];  // n- . v+ = -(n+ . v+)
+    nvp = -nbt[Dims<N>::TRC];  // n- . v+ = -(n+ . v+)
   } else if (c.nb == -1) {  // rigid wall
     pp = pm;
     nvp = -nvm;
@@ -214,12 +218,17 @@ __device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np
   }
 }
 
-template <int N, int MODE, bool QLDS = false>
+// QROW > 0: the old state comes from an LDS tile [4 QROW][16] (field c, node n at row c QROW + n)
+// instead of global memory; HLDS: the two older rhs come from LDS tiles [4 Np][16] (sh1, sh2).
+// TR2 (needs both): no per-lane trace stores; the new state replaces the old one in sq and the
+// half-step state replaces the second rhs in sh2, for tile_traces to write the traces from.
+template <int N, int MODE, int QROW = 0, bool HLDS = false, bool TR2 = false>
 __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
-                                          int64_t m, int flag, const float *sq, int e,
+                                          int64_t m, int flag, float *sq, int e,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
                                           v4f (&rp)[Dims<N>::NR], v4f (&rvx)[Dims<N>::NR], v4f (&rvy)[Dims<N>::NR],
-                                          v4f (&rvz)[Dims<N>::NR]) {
+                                          v4f (&rvz)[Dims<N>::NR], const float *sh1 = nullptr,
+                                          float *sh2 = nullptr) {
   constexpr Tab<N> T{};
   constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F, NR = Dims<N>::NR;
   const int64_t K = a.Ktot;
@@ -282,8 +291,9 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
   float *__restrict__ R0 = sl.ring + (m % 3) * slab;
   const float *__restrict__ R1 = sl.ring + ((m + 2) % 3) * slab;
   const float *__restrict__ R2 = sl.ring + ((m + 1) % 3) * slab;
-  float *__restrict__ trw = sl.tr + ((m + 1) & 1) * (int64_t)2 * F * K;
-  float *__restrict__ trm = sl.tr + (int64_t)2 * 2 * F * K;
+  constexpr int FS = Dims<N>::FS, TRC = Dims<N>::TRC, TRS = Dims<N>::TRS;
+  float *__restrict__ trw = sl.tr + ((m + 1) & 1) * (int64_t)TRS * K;
+  float *__restrict__ trm = sl.tr + (int64_t)2 * TRS * K;
   const bool mid = (flag & 2) != 0;
   float *q = sl.q;
   const float ux = sl.up[0], uy = sl.up[1], uz = sl.up[2];
@@ -318,9 +328,14 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t idx = (int64_t)(c * Np + (ok ? n : 0)) * K + k;
-        h1[i][c] = ok ? R1[idx] : 0.f;
-        h2[i][c] = ok ? R2[idx] : 0.f;
-        if constexpr (QLDS) qo[i][c] = sq[(c * Dims<N>::QR + (ok ? n : 0)) * 16 + e];
+        if constexpr (HLDS) {
+          h1[i][c] = sh1[(c * Np + (ok ? n : 0)) * 16 + e];
+          h2[i][c] = sh2[(c * Np + (ok ? n : 0)) * 16 + e];
+        } else {
+          h1[i][c] = ok ? R1[idx] : 0.f;
+          h2[i][c] = ok ? R2[idx] : 0.f;
+        }
+        if constexpr (QROW > 0) qo[i][c] = sq[(c * QROW + (ok ? n : 0)) * 16 + e];
         else qo[i][c] = ok ? q[idx] : 0.f;
       }
       if constexpr (MODE == MODE_IMAGE) {
@@ -348,6 +363,10 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         qn[c] = qo[i][c] + dtl * (kA0 * r[c] + kA1 * h1[i][c] + kA2 * h2[i][c]);
         q[idx] = qn[c];
         qm[c] = qo[i][c] + dtl * (kB0 * r[c] + kB1 * h1[i][c] + kB2 * h2[i][c]);
+        if constexpr (TR2) {
+          sq[(c * QROW + n) * 16 + e] = qn[c];
+          if (mid) sh2[(c * Np + n) * 16 + e] = qm[c];
+        }
       }
       if constexpr (MODE == MODE_RECORD_SEG) {
         const float qminus = qo[i][0] - zs * (ux * qo[i][1] + uy * qo[i][2] + uz * qo[i][3]);
@@ -373,13 +392,14 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
           sl.img[(int64_t)n * K + k] = imv[i] + dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
         }
       }
+      if constexpr (TR2) continue;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const int fi = sel4(g, T.fidx[min(16 * rt + i, Np - 1)][f], T.fidx[min(16 * rt + 4 + i, Np - 1)][f],
                             T.fidx[min(16 * rt + 8 + i, Np - 1)][f], T.fidx[min(16 * rt + 12 + i, Np - 1)][f]);
         if (fi >= 0) {
-          const int64_t r0 = (int64_t)k * 2 * F + f * Nfp + fi;
-          const int64_t r1 = r0 + F;
+          const int64_t r0 = (int64_t)k * TRS + f * FS + fi;
+          const int64_t r1 = r0 + TRC;
           trw[r0] = qn[0];
           trw[r1] = nfx[f] * qn[1] + nfy[f] * qn[2] + nfz[f] * qn[3];
           if (mid) {
@@ -388,6 +408,51 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
           }
         }
       }
+    }
+  }
+}
+
+// Traces of the new state (and of the half step, for elements with a finer neighbour) from the
+// LDS tiles left by tile_tail<..., TR2>: lane (e, g) writes face g of element e, one 16-byte store
+// per 4 face nodes (the face runs are 16-byte aligned; the padding after the last node is written
+// with zeros and never read).
+template <int N>
+__device__ __forceinline__ void tile_traces(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int e, int64_t m,
+                                            int flag, const float *sq, const float *sqm, const float (&nfx)[4],
+                                            const float (&nfy)[4], const float (&nfz)[4]) {
+  constexpr Tab<N> T{};
+  constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, FS = Dims<N>::FS, TRC = Dims<N>::TRC, TRS = Dims<N>::TRS;
+  if (!(flag & 1)) return;
+  const int64_t K = a.Ktot;
+  const bool mid = (flag & 2) != 0;
+  const float nx = g == 0 ? nfx[0] : (g == 1 ? nfx[1] : (g == 2 ? nfx[2] : nfx[3]));
+  const float ny = g == 0 ? nfy[0] : (g == 1 ? nfy[1] : (g == 2 ? nfy[2] : nfy[3]));
+  const float nz = g == 0 ? nfz[0] : (g == 1 ? nfz[1] : (g == 2 ? nfz[2] : nfz[3]));
+  float *trw = sl.tr + ((m + 1) & 1) * (int64_t)TRS * K + k * TRS + g * FS;
+  float *trm = sl.tr + (int64_t)2 * TRS * K + k * TRS + g * FS;
+#pragma unroll
+  for (int j = 0; j < FS / 4; ++j) {
+    float p[4], v[4], pm[4], vm[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = 4 * j + u;
+      p[u] = v[u] = pm[u] = vm[u] = 0.0f;
+      if (s < Nfp) {
+        const int node = sel4(g, T.fmask[0][s], T.fmask[1][s], T.fmask[2][s], T.fmask[3][s]);
+        p[u] = sq[node * 16 + e];
+        v[u] = nx * sq[(Np + node) * 16 + e] + ny * sq[(2 * Np + node) * 16 + e] + nz * sq[(3 * Np + node) * 16 + e];
+        if (mid) {
+          pm[u] = sqm[node * 16 + e];
+          vm[u] = nx * sqm[(Np + node) * 16 + e] + ny * sqm[(2 * Np + node) * 16 + e] +
+                  nz * sqm[(3 * Np + node) * 16 + e];
+        }
+      }
+    }
+    *reinterpret_cast<float4 *>(trw + 4 * j) = float4{p[0], p[1], p[2], p[3]};
+    *reinterpret_cast<float4 *>(trw + TRC + 4 * j) = float4{v[0], v[1], v[2], v[3]};
+    if (mid) {
+      *reinterpret_cast<float4 *>(trm + 4 * j) = float4{pm[0], pm[1], pm[2], pm[3]};
+      *reinterpret_cast<float4 *>(trm + TRC + 4 * j) = float4{vm[0], vm[1], vm[2], vm[3]};
     }
   }
 }
@@ -481,7 +546,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
       const int nb = nbv[f], code = codev[f];
       const int f2 = code & 3, perm = (code >> 2) & 7, shn = a.L - (code >> 5);
       const int slot = nb >= 0 ? (((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2) : 0;
-      const float *trp = sl.tr + (int64_t)slot * 2 * F * K;
+      const float *trp = sl.tr + (int64_t)slot * Dm::TRS * K;
       const int8_t *tab = stab + ((f * 4 + f2) * 6 + perm) * Nfp;
 #pragma unroll
       for (int cc = 0; cc < FC; ++cc) {
@@ -489,9 +554,9 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
         ntp[f][cc] = 0.f;
         ntv[f][cc] = 0.f;
         if (nb >= 0 && (4 * cc + 3 < Nfp || s < Nfp)) {
-          const float *nbt = trp + (int64_t)nb * 2 * F + f2 * Nfp + tab[s];
+          const float *nbt = trp + (int64_t)nb * Dm::TRS + f2 * Dm::FS + tab[s];
           ntp[f][cc] = nbt[0];
-          ntv[f][cc] = nbt[F];
+          ntv[f][cc] = nbt[Dm::TRC];
         }
       }
     }
@@ -593,7 +658,290 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
           rvz[rt][i] -= nz * G[rt][i];
         }
     }
-    tile_tail<N, MODE, true>(a, sl, k, g, lev, sh, m, flag, sq, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    tile_tail<N, MODE, Dm::QR>(a, sl, k, g, lev, sh, m, flag, sq, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Pipelined form for N <= 4 (FP32).  Same tile mapping, MFMA layout and arithmetic as
+// step_kernel; what changes is how the data reaches the wavefront.
+//  - The volume operator fragments live in registers for the whole kernel (81 per lane at N = 4;
+//    the matrix cores read their A operand from there) and the LIFT fragments in LDS (12 KB),
+//    which leaves room in LDS for the data tiles.
+//  - Everything a tile reads in bulk is copied HBM -> LDS by global_load_lds (no registers hold
+//    data in flight): its fields, geometric factors and the two older rhs as element-contiguous
+//    rows (16 rows of 16 elements per 16-byte instruction), and the neighbour traces as 4-byte
+//    gathers (one instruction per face, face-node chunk and component).
+//  - The copies of tile t+1 are issued as soon as tile t has finished reading the LDS tiles, in
+//    the order fields, geometry, neighbour traces, history; the tile then waits only for what it
+//    needs first, so the history arrives while the operator products run.
+// The copies are issued from inline assembly and every wait on them is explicit: vmcnt counts
+// vector-memory instructions in issue order, so "at most n outstanding" means everything but the
+// last n issued has landed.  The compiler's own waits cover only the loads it can see (element
+// ids and flags, source data), which makes them at worst stricter in hardware, never weaker.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+  return (uint32_t)(size_t)((__attribute__((address_space(3))) const void *)p);
+}
+// 16 bytes per lane to LDS at lds + 16 lane (lds wave-uniform)
+__device__ __forceinline__ void lds_copy16(const void *g, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g),
+               "s"(__builtin_amdgcn_readfirstlane(lds))
+               : "memory", "m0");
+}
+// 4 bytes per lane to LDS at lds + 4 lane (lds wave-uniform)
+__device__ __forceinline__ void lds_copy4(const void *g, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(g),
+               "s"(__builtin_amdgcn_readfirstlane(lds))
+               : "memory", "m0");
+}
+#define DGRTM_WAIT_VM(n) asm volatile("s_waitcnt vmcnt(" #n ")" ::: "memory")
+
+// rows r < ROWS of 16 consecutive floats at src + r*K (16-byte aligned) -> lds[16 r .. 16 r + 15]
+template <int ROWS>
+__device__ __forceinline__ void copy_rows(const float *src, int64_t K, uint32_t lds, int lane) {
+#pragma unroll
+  for (int j = 0; j < (ROWS + 15) / 16; ++j) {
+    const int r = 16 * j + (lane >> 2);
+    if (ROWS % 16 == 0 || r < ROWS) lds_copy16(src + (int64_t)r * K + 4 * (lane & 3), lds + 1024 * j);
+  }
+}
+
+template <int N>
+struct DmaDims {
+  static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, FC = Dims<N>::FC;
+  static constexpr int QW = 4 * Np * 16;             // floats of one wavefront's field tile
+  static constexpr int GW = kGeo * 16;               // geometry tile
+  static constexpr int TW = 4 * FC * 2 * 64;         // neighbour traces [face][chunk][p, n.v][lane]
+  static constexpr int NQ = (4 * Np + 15) / 16;      // 16-byte copies of a field tile
+  static constexpr int NG = (kGeo + 15) / 16;        // ... of the geometry tile
+  static constexpr int NT = 4 * FC * 2;              // 4-byte gathers of the neighbour traces
+  static constexpr int WAVE = QW + GW + TW + 2 * QW; // LDS floats per wavefront (history last)
+};
+
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
+  constexpr Tab<N> T{};
+  using Dm = Dims<N>;
+  using DD = DmaDims<N>;
+  constexpr int Np = Dm::Np, Nfp = Dm::Nfp, F = Dm::F, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
+  constexpr int QW = DD::QW;
+  constexpr bool HIST = MODE != MODE_RHS_ONLY;
+  __shared__ __align__(16) uint32_t stabw[Dm::TABW];
+  __shared__ __align__(16) float sL[NR * 4 * FC * 64];
+  __shared__ __align__(16) float stile[4][DD::WAVE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = lane & 15, g = lane >> 4;
+  // volume operator fragments -> registers (A operands of every volume product of every tile)
+  float fD[3][NR][NK];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+      for (int c = 0; c < NK; ++c) fD[j][rt][c] = a.ops[((j * NR + rt) * NK + c) * 64 + lane];
+  stage_to_lds<NR * 4 * FC * 64>(a.ops + 3 * NR * NK * 64, sL);
+  stage_to_lds<Dm::TABW>(a.nbr_index, stabw);
+  __syncthreads();
+  const int8_t *stab = reinterpret_cast<const int8_t *>(stabw);
+  const int64_t K = a.Ktot;
+  const int64_t ntiles = a.k_end >> 4;
+  const SlotArgs &sl = a.slot[blockIdx.y];
+  const int64_t tstride = 4 * (int64_t)gridDim.x;
+  int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  if (tile >= ntiles) return;
+  float *const q_t = stile[wave];
+  float *const g_t = q_t + QW;
+  float *const n_t = g_t + DD::GW;
+  float *const h_t = n_t + DD::TW;
+  const uint32_t lq = __builtin_amdgcn_readfirstlane(lds_addr(q_t));
+  const uint32_t lg = lq + 4 * QW, ln = lg + 4 * DD::GW, lh = ln + 4 * DD::TW;
+
+  int nbv[4], codev[4], flag;
+  auto load_elem = [&](int64_t t, int (&nb)[4], int (&cd)[4], int &fl) {
+    const int64_t kk = t * 16 + e;
+    fl = sl.eflag[kk];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      nb[f] = a.nbr[f * K + kk];
+      cd[f] = a.ncode[f * K + kk];
+    }
+  };
+  auto issue_tile = [&](int64_t t) {
+    const int64_t k0 = t * 16;
+    copy_rows<4 * Np>(sl.q + k0, K, lq, lane);
+    copy_rows<kGeo>(a.geo + k0, K, lg, lane);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int nb = nbv[f], code = codev[f];
+      const int f2 = code & 3, perm = (code >> 2) & 7, shn = a.L - (code >> 5);
+      const int slot = nb >= 0 ? (((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2) : 0;
+      const float *trp = sl.tr + (int64_t)slot * Dm::TRS * K;
+      const int8_t *tab = stab + ((f * 4 + f2) * 6 + perm) * Nfp;
+#pragma unroll
+      for (int cc = 0; cc < FC; ++cc) {
+        const int s = 4 * cc + g;
+        if (nb >= 0 && (4 * cc + 3 < Nfp || s < Nfp)) {
+          const float *nbt = trp + (int64_t)nb * Dm::TRS + f2 * Dm::FS + tab[s];
+          lds_copy4(nbt, ln + 4 * ((f * FC + cc) * 2 + 0) * 64);
+          lds_copy4(nbt + Dm::TRC, ln + 4 * ((f * FC + cc) * 2 + 1) * 64);
+        }
+      }
+    }
+    if constexpr (HIST) {
+      const int lev = level_of(a.lev_begin, a.L, k0);
+      const int64_t m = sl.tau >> (a.L - lev);
+      const int64_t slab = (int64_t)4 * Np * K;
+      copy_rows<4 * Np>(sl.ring + ((m + 2) % 3) * slab + k0, K, lh, lane);
+      copy_rows<4 * Np>(sl.ring + ((m + 1) % 3) * slab + k0, K, lh + 4 * QW, lane);
+    }
+  };
+  load_elem(tile, nbv, codev, flag);
+  asm volatile("" : "+v"(flag));   // consumed here, so no wait for it lands inside the loop
+  issue_tile(tile);
+
+  while (true) {
+    // fields, geometry and neighbour traces have landed; the history copies may be in flight
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (HIST) {
+      static_assert(2 * DD::NQ == 18 || 2 * DD::NQ == 10 || 2 * DD::NQ == 6 || 2 * DD::NQ == 2, "history copies");
+      if constexpr (2 * DD::NQ == 18) DGRTM_WAIT_VM(18);
+      else if constexpr (2 * DD::NQ == 10) DGRTM_WAIT_VM(10);
+      else if constexpr (2 * DD::NQ == 6) DGRTM_WAIT_VM(6);
+      else DGRTM_WAIT_VM(2);
+    } else {
+      DGRTM_WAIT_VM(0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t k = tile * 16 + e;
+    const int64_t nxt = tile + tstride;
+    int nbn[4], coden[4], flagn = 0;
+    if (nxt < ntiles) load_elem(nxt, nbn, coden, flagn);   // lands while this tile computes
+    const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
+    const int sh = a.L - lev;
+    const int64_t m = sl.tau >> sh;
+
+    float gg[kGeo];
+#pragma unroll
+    for (int i = 0; i < kGeo; ++i) gg[i] = g_t[i * 16 + e];
+    const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
+                tz = gg[8];
+    const float rc2 = gg[9], irho = gg[10];
+
+    // ---- volume: Cp = sum_j D_j U_j and W_j = D_j p
+    v4f cp[NR], w0[NR], w1[NR], w2[NR];
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+      const int mm = 4 * c + g;
+      const bool ok = 4 * c + 3 < Np || mm < Np;
+      const int mr = ok ? mm : 0;
+      const float p = ok ? q_t[mr * 16 + e] : 0.f;
+      const float vx = ok ? q_t[(Np + mr) * 16 + e] : 0.f;
+      const float vy = ok ? q_t[(2 * Np + mr) * 16 + e] : 0.f;
+      const float vz = ok ? q_t[(3 * Np + mr) * 16 + e] : 0.f;
+      const float Ur = rx * vx + ry * vy + rz * vz;
+      const float Us = sx * vx + sy * vy + sz * vz;
+      const float Ut = tx * vx + ty * vy + tz * vz;
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt) {
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[0][rt][c], Ur, cp[rt], 0, 0, 0);
+        w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[0][rt][c], p, w0[rt], 0, 0, 0);
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[1][rt][c], Us, cp[rt], 0, 0, 0);
+        w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[1][rt][c], p, w1[rt], 0, 0, 0);
+        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[2][rt][c], Ut, cp[rt], 0, 0, 0);
+        w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[2][rt][c], p, w2[rt], 0, 0, 0);
+      }
+    }
+    v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
+    volume_to_rhs<NR>(gg, cp, w0, w1, w2, rp, rvx, rvy, rvz);
+
+    // ---- surface: rp -= LIFT Pp (accumulated by the MFMA with -Pp), G_f = LIFT_f Pv, rv -= n_f G_f
+    float nfx[4], nfy[4], nfz[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      float nx, ny, nz;
+      if (f == 0) { nx = -tx; ny = -ty; nz = -tz; }
+      else if (f == 1) { nx = -sx; ny = -sy; nz = -sz; }
+      else if (f == 2) { nx = rx + sx + tx; ny = ry + sy + ty; nz = rz + sz + tz; }
+      else { nx = -rx; ny = -ry; nz = -rz; }
+      const float Fs = sqrtf(nx * nx + ny * ny + nz * nz);  // J_f / J
+      const float inv = 1.0f / Fs;
+      nx *= inv; ny *= inv; nz *= inv;
+      nfx[f] = nx; nfy[f] = ny; nfz[f] = nz;
+      const int nb = nbv[f];
+      const float taup = a.tau_sign * gg[12 + f], tauv = a.tau_sign * gg[16 + f];
+      v4f G[NR];
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int cc = 0; cc < FC; ++cc) {
+        const int s = 4 * cc + g;   // face node handled by this lane in this chunk
+        float mPp = 0.f, Pv = 0.f;
+        if (4 * cc + 3 < Nfp || s < Nfp) {
+          const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
+                                T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
+          const float pm = q_t[node * 16 + e];
+          const float nvm = nx * q_t[(Np + node) * 16 + e] + ny * q_t[(2 * Np + node) * 16 + e] +
+                            nz * q_t[(3 * Np + node) * 16 + e];
+          float pp, nvp;
+          if (nb >= 0) {
+            pp = n_t[((f * FC + cc) * 2 + 0) * 64 + lane];
+            nvp = -n_t[((f * FC + cc) * 2 + 1) * 64 + lane];  // n- . v+ = -(n+ . v+)
+          } else if (nb == -1) {  // rigid wall
+            pp = pm;
+            nvp = -nvm;
+          } else if (nb == -2) {  // transparent
+            pp = 0.0f;
+            nvp = 0.0f;
+          } else {  // free surface
+            pp = -pm;
+            nvp = nvm;
+          }
+          const float dp = pp - pm, dnv = nvp - nvm;
+          mPp = -0.5f * rc2 * (dnv - taup * dp) * Fs;
+          Pv = 0.5f * irho * (dp - tauv * dnv) * Fs;
+        }
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt) {
+          const float al = sL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
+          rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
+          G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          rvx[rt][i] -= nx * G[rt][i];
+          rvy[rt][i] -= ny * G[rt][i];
+          rvz[rt][i] -= nz * G[rt][i];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    DGRTM_WAIT_VM(0);   // the history copies (and the next tile's element data) have landed
+    __builtin_amdgcn_sched_barrier(0);
+    // consume the next tile's element data now, while nothing else is in flight: a wait for it
+    // after the update's stores would also wait for those stores
+#pragma unroll
+    for (int f = 0; f < 4; ++f) asm volatile("" : "+v"(nbn[f]), "+v"(coden[f]));
+    asm volatile("" : "+v"(flagn));
+    tile_tail<N, MODE, Np, HIST, HIST>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy,
+                                       rvz, h_t, h_t + QW);
+    if constexpr (HIST) tile_traces<N>(a, sl, k, g, e, m, flag, q_t, h_t + QW, nfx, nfy, nfz);
+    if (nxt >= ntiles) break;
+    // every LDS access of this tile has completed before the next tile's copies may land
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    tile = nxt;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      nbv[f] = nbn[f];
+      codev[f] = coden[f];
+    }
+    flag = flagn;
+    issue_tile(tile);
   }
 }
 
@@ -863,7 +1211,8 @@ __global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) 
   if (!(a.eflag[k] & 1)) return;
   const int lev = level_of(a.lev_begin, a.L, k);
   const int64_t m = a.tau >> (a.L - lev);
-  float *tr = a.tr + (m & 1) * (int64_t)2 * F * K;
+  constexpr int FS = Dims<N>::FS, TRC = Dims<N>::TRC, TRS = Dims<N>::TRS;
+  float *tr = a.tr + (m & 1) * (int64_t)TRS * K;
   float g[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) g[i] = a.geo[i * K + k];
@@ -883,8 +1232,8 @@ __global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) 
       const float vx = a.q[(int64_t)(Np + node) * K + k];
       const float vy = a.q[(int64_t)(2 * Np + node) * K + k];
       const float vz = a.q[(int64_t)(3 * Np + node) * K + k];
-      tr[(int64_t)k * 2 * F + f * Nfp + i] = p;
-      tr[(int64_t)k * 2 * F + F + f * Nfp + i] = nx * vx + ny * vy + nz * vz;
+      tr[(int64_t)k * TRS + f * FS + i] = p;
+      tr[(int64_t)k * TRS + TRC + f * FS + i] = nx * vx + ny * vy + nz * vz;
     }
   }
 }
@@ -1035,6 +1384,11 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
     } else {
       hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, false>), grid, block, 0, st, a);
     }
+  } else if constexpr (N <= 4) {
+    // one work-group per CU (its static LDS fills the CU); each loops over tile groups
+    const dim3 gridp((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
+                     (unsigned)a.nslots);
+    hipLaunchKernelGGL((step_kernel_dma<N, MODE>), gridp, block, 0, st, a);
   } else if constexpr (lds <= 128 * 1024) {
     static bool done = false;
     hipError_t e = ensure_lds(step_kernel<N, MODE, true>, lds, done);

@@ -4,7 +4,8 @@
 // segment padded to a multiple of 64 so a wavefront never straddles two levels):
 //   q     [4][Np][Ktot]            p, vx, vy, vz
 //   ring  [3][4][Np][Ktot]         AB3 right-hand-side history, slot = own step index mod 3
-//   tr    [3][Ktot][2][4*Nfp]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step
+//   tr    [3][Ktot][2][4][FS]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step;
+//                                  face f's Nfp values start at f*FS, FS = Nfp rounded up to 4
 //   geo   [kGeo][Ktot]             rx ry rz sx sy sz tx ty tz, rho c^2, 1/rho, Z, tau_p[4], tau_v[4]
 //   nbr   [4][Ktot]                neighbour position, or -(boundary type) on a boundary face
 //   ncode [4][Ktot]                neighbour face | vertex permutation << 2 | neighbour level << 5
@@ -22,6 +23,11 @@ constexpr int kMaxLevels = 8;
 enum StepMode : int { MODE_PLAIN = 0, MODE_RECORD_SEG = 1, MODE_IMAGE = 2, MODE_RHS_ONLY = 3 };
 
 constexpr int kMaxSlots = 8;
+
+// face stride of a trace row: Nfp rounded up to a multiple of 4 floats (16-byte aligned runs)
+__host__ __device__ constexpr int trace_face_stride(int Nfp) { return (Nfp + 3) & ~3; }
+// floats of one element's trace row (two components, four faces)
+__host__ __device__ constexpr int trace_row(int Nfp) { return 8 * trace_face_stride(Nfp); }
 
 // Per-shot ("slot") part of a step launch: several shots on the same mesh, at the same phase of
 // their global step, share one launch (blockIdx.y selects the slot).
