@@ -204,15 +204,15 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
   for (int64_t s = 0; s < K; ++s) {
     int64_t u = h.sorted_to_user[s];
     if (u < 0) {
-      geo[0 * K + s] = geo[4 * K + s] = geo[8 * K + s] = 1.0f;
-      geo[9 * K + s] = geo[10 * K + s] = geo[11 * K + s] = 1.0f;
+      geo[tix(kGeo, 0, s)] = geo[tix(kGeo, 4, s)] = geo[tix(kGeo, 8, s)] = 1.0f;
+      geo[tix(kGeo, 9, s)] = geo[tix(kGeo, 10, s)] = geo[tix(kGeo, 11, s)] = 1.0f;
       continue;
     }
-    for (int i = 0; i < 9; ++i) geo[i * K + s] = (float)h.geo[9 * u + i];
+    for (int i = 0; i < 9; ++i) geo[tix(kGeo, i, s)] = (float)h.geo[9 * u + i];
     const double Zm = h.rho[u] * h.c[u];
-    geo[9 * K + s] = (float)(h.rho[u] * h.c[u] * h.c[u]);
-    geo[10 * K + s] = (float)(1.0 / h.rho[u]);
-    geo[11 * K + s] = (float)Zm;
+    geo[tix(kGeo, 9, s)] = (float)(h.rho[u] * h.c[u] * h.c[u]);
+    geo[tix(kGeo, 10, s)] = (float)(1.0 / h.rho[u]);
+    geo[tix(kGeo, 11, s)] = (float)Zm;
     int flag = 1;
     for (int f = 0; f < 4; ++f) {
       const int64_t u2 = h.EToE[4 * u + f];
@@ -221,17 +221,17 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
       if (b_ != 0) {
         taup = 1.0 / Zm;
         tauv = Zm;
-        nbr[f * K + s] = -b_;
+        nbr[tix(4, f, s)] = -b_;
       } else {
         const double Zp = h.rho[u2] * h.c[u2];
         taup = 2.0 / (Zm + Zp);
         tauv = 0.5 * (Zm + Zp);
-        nbr[f * K + s] = (int)h.user_to_sorted[u2];
-        ncode[f * K + s] = h.EToF[4 * u + f] | (h.face_perm[4 * u + f] << 2) | (h.level[u2] << 5);
+        nbr[tix(4, f, s)] = (int)h.user_to_sorted[u2];
+        ncode[tix(4, f, s)] = h.EToF[4 * u + f] | (h.face_perm[4 * u + f] << 2) | (h.level[u2] << 5);
         if (h.level[u2] > h.level[u]) flag |= 2;
       }
-      geo[(12 + f) * K + s] = (float)taup;
-      geo[(16 + f) * K + s] = (float)tauv;
+      geo[tix(kGeo, 12 + f, s)] = (float)taup;
+      geo[tix(kGeo, 16 + f, s)] = (float)tauv;
     }
     m->h_eflag[s] = flag;
   }
@@ -723,13 +723,13 @@ static dgrtm_status ckpt_copy(dgrtm_shot sh, Field &f, int64_t c, bool save) {
     const int64_t b0 = h.lev_begin[l - 1], P = level_size_h(h, l);
     if (P == 0) continue;
     for (int s = 1; s <= 2; ++s) {
+      // a level is a whole number of tiles, hence one contiguous block of the tiled layout
       const int64_t slot = ((mstep - s) % 3 + 3) % 3;
-      float *ring = f.ring + slot * slab + b0;
-      float *cks = ck + s * slab + b0;
-      if (save)
-        HIPCHK(hipMemcpy2DAsync(cks, K * 4, ring, K * 4, P * 4, 4 * Np, hipMemcpyDeviceToDevice, st));
-      else
-        HIPCHK(hipMemcpy2DAsync(ring, K * 4, cks, K * 4, P * 4, 4 * Np, hipMemcpyDeviceToDevice, st));
+      float *ring = f.ring + slot * slab + tix(4 * Np, 0, b0);
+      float *cks = ck + s * slab + tix(4 * Np, 0, b0);
+      const size_t bytes = (size_t)P * 4 * Np * sizeof(float);
+      if (save) HIPCHK(hipMemcpyAsync(cks, ring, bytes, hipMemcpyDeviceToDevice, st));
+      else HIPCHK(hipMemcpyAsync(ring, cks, bytes, hipMemcpyDeviceToDevice, st));
     }
   }
   return DGRTM_OK;

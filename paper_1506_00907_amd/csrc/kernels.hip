@@ -60,8 +60,6 @@ struct Dims {
   static constexpr int NK = (Np + 3) / 4;     // 4-column chunks of D_j
   static constexpr int FC = (Nfp + 3) / 4;    // 4-column chunks per face of LIFT
   static constexpr int OPS = (3 * NR * NK + NR * 4 * FC) * 64;   // operator fragment floats
-  static constexpr int QR = 4 * NK;                               // rows per field of an LDS q tile
-  static constexpr int QT = 4 * QR * 16;                          // floats of one wavefront's q tile
   static constexpr int TABW = (4 * 4 * 6 * Nfp + 3) / 4;          // face-node map, in 32-bit words
   static constexpr int FS = trace_face_stride(Nfp);               // trace row: face stride,
   static constexpr int TRC = 4 * FS;                              // component stride,
@@ -154,8 +152,8 @@ __device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, const SlotArgs &s
   c.Fs = sqrtf(nx * nx + ny * ny + nz * nz);  // J_f / J
   const float inv = 1.0f / c.Fs;
   c.nx = nx * inv; c.ny = ny * inv; c.nz = nz * inv;
-  c.nb = a.nbr[f * K + k];
-  const int code = a.ncode[f * K + k];
+  c.nb = a.nbr[tix(4, f, k)];
+  const int code = a.ncode[tix(4, f, k)];
   c.taup = a.tau_sign * gg[12 + f];
   c.tauv = a.tau_sign * gg[16 + f];
   c.trp = sl.tr;
@@ -180,9 +178,9 @@ __device__ __forceinline__ void penalty(const StepArgs &a, const float *q, const
                                         float rc2, float irho, float &mPp, float &Pv) {
   constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F;
   const int64_t K = a.Ktot;
-  const float pm = q[(int64_t)node * K + k];
-  const float nvm = c.nx * q[(int64_t)(Np + node) * K + k] + c.ny * q[(int64_t)(2 * Np + node) * K + k] +
-                    c.nz * q[(int64_t)(3 * Np + node) * K + k];
+  const float pm = q[tix(4 * Np, node, k)];
+  const float nvm = c.nx * q[tix(4 * Np, Np + node, k)] + c.ny * q[tix(4 * Np, 2 * Np + node, k)] +
+                    c.nz * q[tix(4 * Np, 3 * Np + node, k)];
   float pp, nvp;
   if (c.nb >= 0) {
     const float *nbt = c.trp + (int64_t)c.nb * Dims<N>::TRS + c.f2 * Dims<N>::FS + c.tab[s];
@@ -220,14 +218,15 @@ __device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np
 
 // QROW > 0: the old state comes from an LDS tile [4 QROW][16] (field c, node n at row c QROW + n)
 // instead of global memory; HLDS: the two older rhs come from LDS tiles [4 Np][16] (sh1, sh2).
-// TR2 (needs both): no per-lane trace stores; the new state replaces the old one in sq and the
-// half-step state replaces the second rhs in sh2, for tile_traces to write the traces from.
+// TR2 (needs both): no per-lane stores of the state, the rhs or the traces; the new state replaces
+// the old one in sq, the new rhs the first older rhs in sh1 and the half-step state the second in
+// sh2, for tile_traces and store_rows to write out with 16-byte stores.
 template <int N, int MODE, int QROW = 0, bool HLDS = false, bool TR2 = false>
 __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
                                           int64_t m, int flag, float *sq, int e,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
                                           v4f (&rp)[Dims<N>::NR], v4f (&rvx)[Dims<N>::NR], v4f (&rvy)[Dims<N>::NR],
-                                          v4f (&rvz)[Dims<N>::NR], const float *sh1 = nullptr,
+                                          v4f (&rvz)[Dims<N>::NR], float *sh1 = nullptr,
                                           float *sh2 = nullptr) {
   constexpr Tab<N> T{};
   constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F, NR = Dims<N>::NR;
@@ -278,10 +277,10 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       for (int i = 0; i < 4; ++i) {
         const int n = 16 * rt + 4 * g + i;
         if (16 * rt + 15 < Np || n < Np) {
-          sl.rhs_out[(int64_t)(0 * Np + n) * K + k] = rp[rt][i];
-          sl.rhs_out[(int64_t)(1 * Np + n) * K + k] = rvx[rt][i];
-          sl.rhs_out[(int64_t)(2 * Np + n) * K + k] = rvy[rt][i];
-          sl.rhs_out[(int64_t)(3 * Np + n) * K + k] = rvz[rt][i];
+          sl.rhs_out[tix(4 * Np, 0 * Np + n, k)] = rp[rt][i];
+          sl.rhs_out[tix(4 * Np, 1 * Np + n, k)] = rvx[rt][i];
+          sl.rhs_out[tix(4 * Np, 2 * Np + n, k)] = rvy[rt][i];
+          sl.rhs_out[tix(4 * Np, 3 * Np + n, k)] = rvz[rt][i];
         }
       }
     return;
@@ -327,7 +326,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       const bool ok = (16 * rt + 15 < Np || n < Np);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int64_t idx = (int64_t)(c * Np + (ok ? n : 0)) * K + k;
+        const int64_t idx = tix(4 * Np, c * Np + (ok ? n : 0), k);
         if constexpr (HLDS) {
           h1[i][c] = sh1[(c * Np + (ok ? n : 0)) * 16 + e];
           h2[i][c] = sh2[(c * Np + (ok ? n : 0)) * 16 + e];
@@ -346,7 +345,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
           srv[i][0] = srp[((jS + 2) * Np + n) * Pl + kk];
           srv[i][1] = srp[((jS + 1) * Np + n) * Pl + kk];
           srv[i][2] = srp[(jS * Np + n) * Pl + kk];
-          imv[i] = sl.img[(int64_t)n * K + k];
+          imv[i] = sl.img[tix(Np, n, k)];
         }
       }
     }
@@ -358,14 +357,16 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       float qn[4], qm[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int64_t idx = (int64_t)(c * Np + n) * K + k;
-        R0[idx] = r[c];
+        const int64_t idx = tix(4 * Np, c * Np + n, k);
         qn[c] = qo[i][c] + dtl * (kA0 * r[c] + kA1 * h1[i][c] + kA2 * h2[i][c]);
-        q[idx] = qn[c];
         qm[c] = qo[i][c] + dtl * (kB0 * r[c] + kB1 * h1[i][c] + kB2 * h2[i][c]);
-        if constexpr (TR2) {
+        if constexpr (TR2) {   // (these slots were read above and are not read again)
           sq[(c * QROW + n) * 16 + e] = qn[c];
-          if (mid) sh2[(c * Np + n) * 16 + e] = qm[c];
+          sh1[(c * Np + n) * 16 + e] = r[c];
+          sh2[(c * Np + n) * 16 + e] = qm[c];
+        } else {
+          R0[idx] = r[c];
+          q[idx] = qn[c];
         }
       }
       if constexpr (MODE == MODE_RECORD_SEG) {
@@ -389,7 +390,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
           for (int s1 = 0; s1 < 3; ++s1)
 #pragma unroll
             for (int s2 = 0; s2 < 3; ++s2) inc3 += kCm[s1][s2] * rS[s1] * rR[s2];
-          sl.img[(int64_t)n * K + k] = imv[i] + dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
+          sl.img[tix(Np, n, k)] = imv[i] + dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
         }
       }
       if constexpr (TR2) continue;
@@ -441,11 +442,8 @@ __device__ __forceinline__ void tile_traces(const StepArgs &a, const SlotArgs &s
         const int node = sel4(g, T.fmask[0][s], T.fmask[1][s], T.fmask[2][s], T.fmask[3][s]);
         p[u] = sq[node * 16 + e];
         v[u] = nx * sq[(Np + node) * 16 + e] + ny * sq[(2 * Np + node) * 16 + e] + nz * sq[(3 * Np + node) * 16 + e];
-        if (mid) {
-          pm[u] = sqm[node * 16 + e];
-          vm[u] = nx * sqm[(Np + node) * 16 + e] + ny * sqm[(2 * Np + node) * 16 + e] +
-                  nz * sqm[(3 * Np + node) * 16 + e];
-        }
+        pm[u] = sqm[node * 16 + e];
+        vm[u] = nx * sqm[(Np + node) * 16 + e] + ny * sqm[(2 * Np + node) * 16 + e] + nz * sqm[(3 * Np + node) * 16 + e];
       }
     }
     *reinterpret_cast<float4 *>(trw + 4 * j) = float4{p[0], p[1], p[2], p[3]};
@@ -476,195 +474,14 @@ __device__ __forceinline__ void volume_to_rhs(const float *gg, const v4f (&cp)[N
     }
 }
 
-// One wavefront owns a tile of 16 consecutive elements.  The element-batched operator products
-// run on v_mfma_f32_16x16x4_f32: A = 16 operator rows x 4 columns (lane l holds
-// A[l%16][l/16]), B = 4 input nodes x 16 elements (lane l holds B[l/16][l%16]), C = 16 rows x 16
-// elements (lane l holds rows 4(l/16)+i, i=0..3, of element l%16).  All elementwise work
-// (geometric factors, penalties, AB3, traces, image) runs in that C layout: lane l handles the
-// element e = l%16 and, in row tile rt, the nodes n = 16 rt + 4 (l/16) + i.
-//
-// Memory-level parallelism: at the start of a tile every lane issues, in one batch, the loads of
-// its share of the tile's fields and of the neighbour traces it will need, so one memory latency is
-// paid per tile.  The fields are then copied into an LDS tile ([4][QR][16] floats per wavefront),
-// from which the surface terms read their own traces and the update reads q.
-template <int N, int MODE, bool OPS_LDS>
-__global__ __launch_bounds__(256) void step_kernel(const StepArgs a) {
-  constexpr Tab<N> T{};
-  using Dm = Dims<N>;
-  constexpr int Np = Dm::Np, Nfp = Dm::Nfp, F = Dm::F, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC, QR = Dm::QR;
-  extern __shared__ float smem[];
-  const float *ops = a.ops;
-  int8_t *stab = reinterpret_cast<int8_t *>(smem + (OPS_LDS ? Dm::OPS : 0));
-  float *qtiles = smem + (OPS_LDS ? Dm::OPS : 0) + Dm::TABW;
-  if constexpr (OPS_LDS) {
-    stage_to_lds<Dm::OPS>(a.ops, smem);
-    ops = smem;
-  }
-  stage_to_lds<4 * 4 * 6 * Nfp / 4>(a.nbr_index, stab);
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int e = lane & 15, g = lane >> 4;
-  const int64_t K = a.Ktot;
-  const int64_t ntiles = a.k_end >> 4;
-  const SlotArgs &sl = a.slot[blockIdx.y];
-  float *sq = qtiles + wave * Dm::QT;
-
-  for (int64_t grp = blockIdx.x; grp * 4 < ntiles; grp += gridDim.x) {
-    const int64_t tile = grp * 4 + wave;
-    if (tile >= ntiles) continue;
-    const int64_t k = tile * 16 + e;
-    int opaque0;
-    asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
-    const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
-    const float *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;    // [NR][4*FC][64]
-    const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
-    const int sh = a.L - lev;
-    const int64_t m = sl.tau >> sh;
-
-    // ---- batch 1: element data and this lane's share of the tile's fields
-    const int flag = sl.eflag[k];
-    float gg[kGeo];
-#pragma unroll
-    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[i * K + k];
-    int nbv[4], codev[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      nbv[f] = a.nbr[f * K + k];
-      codev[f] = a.ncode[f * K + k];
-    }
-    float qv[NK][4];
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-      const int mm = 4 * c + g;
-#pragma unroll
-      for (int fl = 0; fl < 4; ++fl) qv[c][fl] = (4 * c + 3 < Np || mm < Np) ? sl.q[(int64_t)(fl * Np + mm) * K + k] : 0.f;
-    }
-    // ---- batch 2: neighbour traces of every face node this lane handles
-    float ntp[4][FC], ntv[4][FC];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int nb = nbv[f], code = codev[f];
-      const int f2 = code & 3, perm = (code >> 2) & 7, shn = a.L - (code >> 5);
-      const int slot = nb >= 0 ? (((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2) : 0;
-      const float *trp = sl.tr + (int64_t)slot * Dm::TRS * K;
-      const int8_t *tab = stab + ((f * 4 + f2) * 6 + perm) * Nfp;
-#pragma unroll
-      for (int cc = 0; cc < FC; ++cc) {
-        const int s = 4 * cc + g;
-        ntp[f][cc] = 0.f;
-        ntv[f][cc] = 0.f;
-        if (nb >= 0 && (4 * cc + 3 < Nfp || s < Nfp)) {
-          const float *nbt = trp + (int64_t)nb * Dm::TRS + f2 * Dm::FS + tab[s];
-          ntp[f][cc] = nbt[0];
-          ntv[f][cc] = nbt[Dm::TRC];
-        }
-      }
-    }
-    // the tile's fields into LDS (own traces and the update read them from there)
-#pragma unroll
-    for (int c = 0; c < NK; ++c)
-#pragma unroll
-      for (int fl = 0; fl < 4; ++fl) sq[(fl * QR + 4 * c + g) * 16 + e] = qv[c][fl];
-
-    const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
-                tz = gg[8];
-    const float rc2 = gg[9], irho = gg[10];
-
-    // ---- volume: Cp = sum_j D_j U_j and W_j = D_j p
-    v4f cp[NR], w0[NR], w1[NR], w2[NR];
-#pragma unroll
-    for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-      const float p = qv[c][0], vx = qv[c][1], vy = qv[c][2], vz = qv[c][3];
-      const float Ur = rx * vx + ry * vy + rz * vz;
-      const float Us = sx * vx + sy * vy + sz * vz;
-      const float Ut = tx * vx + ty * vy + tz * vz;
-#pragma unroll
-      for (int rt = 0; rt < NR; ++rt) {
-        const float ar = fD[((0 * NR + rt) * NK + c) * 64 + lane];
-        const float as = fD[((1 * NR + rt) * NK + c) * 64 + lane];
-        const float at = fD[((2 * NR + rt) * NK + c) * 64 + lane];
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, Ur, cp[rt], 0, 0, 0);
-        w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, p, w0[rt], 0, 0, 0);
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, Us, cp[rt], 0, 0, 0);
-        w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, p, w1[rt], 0, 0, 0);
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Ut, cp[rt], 0, 0, 0);
-        w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, p, w2[rt], 0, 0, 0);
-      }
-    }
-    v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
-    volume_to_rhs<NR>(gg, cp, w0, w1, w2, rp, rvx, rvy, rvz);
-
-    // ---- surface: rp -= LIFT Pp (accumulated by the MFMA with -Pp), G_f = LIFT_f Pv, rv -= n_f G_f
-    float nfx[4], nfy[4], nfz[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      float nx, ny, nz;
-      if (f == 0) { nx = -tx; ny = -ty; nz = -tz; }
-      else if (f == 1) { nx = -sx; ny = -sy; nz = -sz; }
-      else if (f == 2) { nx = rx + sx + tx; ny = ry + sy + ty; nz = rz + sz + tz; }
-      else { nx = -rx; ny = -ry; nz = -rz; }
-      const float Fs = sqrtf(nx * nx + ny * ny + nz * nz);  // J_f / J
-      const float inv = 1.0f / Fs;
-      nx *= inv; ny *= inv; nz *= inv;
-      nfx[f] = nx; nfy[f] = ny; nfz[f] = nz;
-      const int nb = nbv[f];
-      const float taup = a.tau_sign * gg[12 + f], tauv = a.tau_sign * gg[16 + f];
-      v4f G[NR];
-#pragma unroll
-      for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int cc = 0; cc < FC; ++cc) {
-        const int s = 4 * cc + g;   // face node handled by this lane in this chunk
-        float mPp = 0.f, Pv = 0.f;
-        if (4 * cc + 3 < Nfp || s < Nfp) {
-          const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
-                                T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
-          const float pm = sq[(0 * QR + node) * 16 + e];
-          const float nvm = nx * sq[(1 * QR + node) * 16 + e] + ny * sq[(2 * QR + node) * 16 + e] +
-                            nz * sq[(3 * QR + node) * 16 + e];
-          float pp, nvp;
-          if (nb >= 0) {
-            pp = ntp[f][cc];
-            nvp = -ntv[f][cc];  // n- . v+ = -(n+ . v+)
-          } else if (nb == -1) {  // rigid wall
-            pp = pm;
-            nvp = -nvm;
-          } else if (nb == -2) {  // transparent
-            pp = 0.0f;
-            nvp = 0.0f;
-          } else {  // free surface
-            pp = -pm;
-            nvp = nvm;
-          }
-          const float dp = pp - pm, dnv = nvp - nvm;
-          mPp = -0.5f * rc2 * (dnv - taup * dp) * Fs;
-          Pv = 0.5f * irho * (dp - tauv * dnv) * Fs;
-        }
-#pragma unroll
-        for (int rt = 0; rt < NR; ++rt) {
-          const float al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
-          rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
-          G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int rt = 0; rt < NR; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          rvx[rt][i] -= nx * G[rt][i];
-          rvy[rt][i] -= ny * G[rt][i];
-          rvz[rt][i] -= nz * G[rt][i];
-        }
-    }
-    tile_tail<N, MODE, Dm::QR>(a, sl, k, g, lev, sh, m, flag, sq, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
-  }
-}
-
 // ------------------------------------------------------------------------------------------
-// Pipelined form for N <= 4 (FP32).  Same tile mapping, MFMA layout and arithmetic as
-// step_kernel; what changes is how the data reaches the wavefront.
+// The FP32 step kernel for N <= 4.  One wavefront owns a tile of 16 consecutive elements.  The
+// element-batched operator products run on v_mfma_f32_16x16x4_f32: A = 16 operator rows x 4
+// columns (lane l holds A[l%16][l/16]), B = 4 input nodes x 16 elements (lane l holds
+// B[l/16][l%16]), C = 16 rows x 16 elements (lane l holds rows 4(l/16)+i, i=0..3, of element
+// l%16).  All elementwise work (geometric factors, penalties, AB3, traces, image) runs in that C
+// layout: lane l handles the element e = l%16 and, in row tile rt, the nodes n = 16 rt + 4 (l/16) + i.
+// The kernel is pipelined across tiles:
 //  - The volume operator fragments live in registers for the whole kernel (81 per lane at N = 4;
 //    the matrix cores read their A operand from there) and the LIFT fragments in LDS (12 KB),
 //    which leaves room in LDS for the data tiles.
@@ -697,14 +514,21 @@ __device__ __forceinline__ void lds_copy4(const void *g, uint32_t lds) {
 }
 #define DGRTM_WAIT_VM(n) asm volatile("s_waitcnt vmcnt(" #n ")" ::: "memory")
 
-// rows r < ROWS of 16 consecutive floats at src + r*K (16-byte aligned) -> lds[16 r .. 16 r + 15]
+// one tile's block of ROWS rows x 16 floats (contiguous, 16-byte aligned) -> LDS, 1 KB per copy
 template <int ROWS>
-__device__ __forceinline__ void copy_rows(const float *src, int64_t K, uint32_t lds, int lane) {
+__device__ __forceinline__ void copy_block(const float *src, uint32_t lds, int lane) {
 #pragma unroll
-  for (int j = 0; j < (ROWS + 15) / 16; ++j) {
-    const int r = 16 * j + (lane >> 2);
-    if (ROWS % 16 == 0 || r < ROWS) lds_copy16(src + (int64_t)r * K + 4 * (lane & 3), lds + 1024 * j);
-  }
+  for (int j = 0; j < (ROWS + 15) / 16; ++j)
+    if (ROWS % 16 == 0 || 16 * j + (lane >> 2) < ROWS) lds_copy16(src + 256 * j + 4 * lane, lds + 1024 * j);
+}
+
+// LDS -> one tile's block of ROWS rows x 16 floats, 16-byte stores
+template <int ROWS>
+__device__ __forceinline__ void store_block(const float *lds, float *dst, int lane) {
+#pragma unroll
+  for (int j = 0; j < (ROWS + 15) / 16; ++j)
+    if (ROWS % 16 == 0 || 16 * j + (lane >> 2) < ROWS)
+      *reinterpret_cast<float4 *>(dst + 256 * j + 4 * lane) = *reinterpret_cast<const float4 *>(lds + 256 * j + 4 * lane);
 }
 
 template <int N>
@@ -712,10 +536,11 @@ struct DmaDims {
   static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, FC = Dims<N>::FC;
   static constexpr int QW = 4 * Np * 16;             // floats of one wavefront's field tile
   static constexpr int GW = kGeo * 16;               // geometry tile
-  static constexpr int TW = 4 * FC * 2 * 64;         // neighbour traces [face][chunk][p, n.v][lane]
+  static constexpr int FS = Dims<N>::FS;
+  static constexpr int TW = 8 * 16 * FS;             // neighbour face runs [face][p, n.v][FS/4][16][4]
   static constexpr int NQ = (4 * Np + 15) / 16;      // 16-byte copies of a field tile
   static constexpr int NG = (kGeo + 15) / 16;        // ... of the geometry tile
-  static constexpr int NT = 4 * FC * 2;              // 4-byte gathers of the neighbour traces
+  static constexpr int NT = 8;                       // 16-byte copies of the neighbour face runs
   static constexpr int WAVE = QW + GW + TW + 2 * QW; // LDS floats per wavefront (history last)
 };
 
@@ -763,37 +588,35 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     fl = sl.eflag[kk];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      nb[f] = a.nbr[f * K + kk];
-      cd[f] = a.ncode[f * K + kk];
+      nb[f] = a.nbr[tix(4, f, kk)];
+      cd[f] = a.ncode[tix(4, f, kk)];
     }
   };
   auto issue_tile = [&](int64_t t) {
     const int64_t k0 = t * 16;
-    copy_rows<4 * Np>(sl.q + k0, K, lq, lane);
-    copy_rows<kGeo>(a.geo + k0, K, lg, lane);
+    copy_block<4 * Np>(sl.q + tix(4 * Np, 0, k0), lq, lane);
+    copy_block<kGeo>(a.geo + tix(kGeo, 0, k0), lg, lane);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       const int nb = nbv[f], code = codev[f];
       const int f2 = code & 3, perm = (code >> 2) & 7, shn = a.L - (code >> 5);
       const int slot = nb >= 0 ? (((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2) : 0;
       const float *trp = sl.tr + (int64_t)slot * Dm::TRS * K;
-      const int8_t *tab = stab + ((f * 4 + f2) * 6 + perm) * Nfp;
-#pragma unroll
-      for (int cc = 0; cc < FC; ++cc) {
-        const int s = 4 * cc + g;
-        if (nb >= 0 && (4 * cc + 3 < Nfp || s < Nfp)) {
-          const float *nbt = trp + (int64_t)nb * Dm::TRS + f2 * Dm::FS + tab[s];
-          lds_copy4(nbt, ln + 4 * ((f * FC + cc) * 2 + 0) * 64);
-          lds_copy4(nbt + Dm::TRC, ln + 4 * ((f * FC + cc) * 2 + 1) * 64);
-        }
+      // lane (g, e) copies nodes 4g .. 4g+3 of the neighbour's face run (in the neighbour's node
+      // order) to [face][component][g][e][4]; the surface terms apply the node permutation
+      if (nb >= 0 && 4 * g < Dm::FS) {
+        const float *run = trp + (int64_t)nb * Dm::TRS + f2 * Dm::FS + 4 * g;
+        lds_copy16(run, ln + 4 * (2 * f + 0) * 16 * Dm::FS);
+        lds_copy16(run + Dm::TRC, ln + 4 * (2 * f + 1) * 16 * Dm::FS);
       }
+      (void)perm;
     }
     if constexpr (HIST) {
       const int lev = level_of(a.lev_begin, a.L, k0);
       const int64_t m = sl.tau >> (a.L - lev);
       const int64_t slab = (int64_t)4 * Np * K;
-      copy_rows<4 * Np>(sl.ring + ((m + 2) % 3) * slab + k0, K, lh, lane);
-      copy_rows<4 * Np>(sl.ring + ((m + 1) % 3) * slab + k0, K, lh + 4 * QW, lane);
+      copy_block<4 * Np>(sl.ring + ((m + 2) % 3) * slab + tix(4 * Np, 0, k0), lh, lane);
+      copy_block<4 * Np>(sl.ring + ((m + 1) % 3) * slab + tix(4 * Np, 0, k0), lh + 4 * QW, lane);
     }
   };
   load_elem(tile, nbv, codev, flag);
@@ -872,37 +695,33 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       nfx[f] = nx; nfy[f] = ny; nfz[f] = nz;
       const int nb = nbv[f];
       const float taup = a.tau_sign * gg[12 + f], tauv = a.tau_sign * gg[16 + f];
+      // exterior state without branches: p+ = cP p- + p_nb and (n-.v)+ = -(cP (n-.v)- + (n_nb.v)_nb),
+      // with p_nb, (n.v)_nb the neighbour's traces on an interior face and 0 on a boundary face;
+      // cP = 1 on a rigid wall, -1 on a free surface, 0 on a transparent or interior face
+      const bool inner = nb >= 0;
+      const float cP = nb == -1 ? 1.0f : (nb == -3 ? -1.0f : 0.0f);
+      const int f2 = inner ? (codev[f] & 3) : 0, perm = inner ? ((codev[f] >> 2) & 7) : 0;
       v4f G[NR];
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int cc = 0; cc < FC; ++cc) {
-        const int s = 4 * cc + g;   // face node handled by this lane in this chunk
-        float mPp = 0.f, Pv = 0.f;
-        if (4 * cc + 3 < Nfp || s < Nfp) {
-          const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
-                                T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
-          const float pm = q_t[node * 16 + e];
-          const float nvm = nx * q_t[(Np + node) * 16 + e] + ny * q_t[(2 * Np + node) * 16 + e] +
-                            nz * q_t[(3 * Np + node) * 16 + e];
-          float pp, nvp;
-          if (nb >= 0) {
-            pp = n_t[((f * FC + cc) * 2 + 0) * 64 + lane];
-            nvp = -n_t[((f * FC + cc) * 2 + 1) * 64 + lane];  // n- . v+ = -(n+ . v+)
-          } else if (nb == -1) {  // rigid wall
-            pp = pm;
-            nvp = -nvm;
-          } else if (nb == -2) {  // transparent
-            pp = 0.0f;
-            nvp = 0.0f;
-          } else {  // free surface
-            pp = -pm;
-            nvp = nvm;
-          }
-          const float dp = pp - pm, dnv = nvp - nvm;
-          mPp = -0.5f * rc2 * (dnv - taup * dp) * Fs;
-          Pv = 0.5f * irho * (dp - tauv * dnv) * Fs;
-        }
+        const bool sv = 4 * cc + 3 < Nfp || 4 * cc + g < Nfp;   // face node 4 cc + g exists
+        const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
+                              T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
+        const float pm = q_t[node * 16 + e];
+        const float nvm = nx * q_t[(Np + node) * 16 + e] + ny * q_t[(2 * Np + node) * 16 + e] +
+                          nz * q_t[(3 * Np + node) * 16 + e];
+        // the neighbour's node matching face node 4 cc + g of this face
+        const int t = stab[((f * 4 + f2) * 6 + perm) * Nfp + min(4 * cc + g, Nfp - 1)];
+        const int toff = (t >> 2) * 64 + e * 4 + (t & 3);
+        const float tp = inner ? n_t[(2 * f + 0) * 16 * Dm::FS + toff] : 0.0f;
+        const float tv = inner ? n_t[(2 * f + 1) * 16 * Dm::FS + toff] : 0.0f;
+        const float pp = cP * pm + tp;
+        const float nvp = -(cP * nvm + tv);
+        const float dp = pp - pm, dnv = nvp - nvm;
+        const float mPp = sv ? -0.5f * rc2 * (dnv - taup * dp) * Fs : 0.0f;
+        const float Pv = sv ? 0.5f * irho * (dp - tauv * dnv) * Fs : 0.0f;
 #pragma unroll
         for (int rt = 0; rt < NR; ++rt) {
           const float al = sL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
@@ -929,7 +748,13 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     asm volatile("" : "+v"(flagn));
     tile_tail<N, MODE, Np, HIST, HIST>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy,
                                        rvz, h_t, h_t + QW);
-    if constexpr (HIST) tile_traces<N>(a, sl, k, g, e, m, flag, q_t, h_t + QW, nfx, nfy, nfz);
+    if constexpr (HIST) {
+      tile_traces<N>(a, sl, k, g, e, m, flag, q_t, h_t + QW, nfx, nfy, nfz);
+      // new state and new rhs of the tile: element-contiguous rows, 16 bytes per lane
+      const int64_t k0 = tile * 16;
+      store_block<4 * Np>(q_t, sl.q + tix(4 * Np, 0, k0), lane);
+      store_block<4 * Np>(h_t, sl.ring + (m % 3) * ((int64_t)4 * Np * K) + tix(4 * Np, 0, k0), lane);
+    }
     if (nxt >= ntiles) break;
     // every LDS access of this tile has completed before the next tile's copies may land
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -945,13 +770,9 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   }
 }
 
-// Lower-register variant for N >= 5 (fields loaded chunk by chunk, no LDS tile), same layout as
-// step_kernel.  One wavefront owns a tile of 16 consecutive elements.  The element-batched operator products
-// run on v_mfma_f32_16x16x4_f32: A = 16 operator rows x 4 columns (lane l holds
-// A[l%16][l/16]), B = 4 input nodes x 16 elements (lane l holds B[l/16][l%16]), C = 16 rows x 16
-// elements (lane l holds rows 4(l/16)+i, i=0..3, of element l%16).  All elementwise work
-// (geometric factors, penalties, AB3, traces, image) runs in that C layout: lane l handles the
-// element e = l%16 and, in row tile rt, the nodes n = 16 rt + 4 (l/16) + i.
+// The FP32 step kernel for N >= 5, with the tile mapping and MFMA layout of step_kernel_dma.  Its
+// operators do not leave room in registers or LDS for the pipelined tiles, so it loads the
+// fields chunk by chunk straight from HBM, with the operator fragments in LDS when they fit.
 template <int N, int MODE, bool OPS_LDS>
 __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   constexpr Tab<N> T{};
@@ -987,7 +808,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
 
     float gg[kGeo];
 #pragma unroll
-    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[i * K + k];
+    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[tix(kGeo, i, k)];
     const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
                 tz = gg[8];
     const float rc2 = gg[9], irho = gg[10];
@@ -1001,10 +822,10 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       const int mm = 4 * c + g;
       float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
       if (mm < Np) {
-        p = sl.q[(int64_t)mm * K + k];
-        vx = sl.q[(int64_t)(Np + mm) * K + k];
-        vy = sl.q[(int64_t)(2 * Np + mm) * K + k];
-        vz = sl.q[(int64_t)(3 * Np + mm) * K + k];
+        p = sl.q[tix(4 * Np, mm, k)];
+        vx = sl.q[tix(4 * Np, Np + mm, k)];
+        vy = sl.q[tix(4 * Np, 2 * Np + mm, k)];
+        vz = sl.q[tix(4 * Np, 3 * Np + mm, k)];
       }
       const float Ur = rx * vx + ry * vy + rz * vz;
       const float Us = sx * vx + sy * vy + sz * vz;
@@ -1111,7 +932,7 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
     const int64_t m = sl.tau >> sh;
     float gg[kGeo];
 #pragma unroll
-    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[i * K + k];
+    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[tix(kGeo, i, k)];
     const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
                 tz = gg[8];
     const float rc2 = gg[9], irho = gg[10];
@@ -1127,10 +948,10 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
         const int mm = 16 * c + 4 * g + v;
         float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
         if (mm < Np) {
-          p = sl.q[(int64_t)mm * K + k];
-          vx = sl.q[(int64_t)(Np + mm) * K + k];
-          vy = sl.q[(int64_t)(2 * Np + mm) * K + k];
-          vz = sl.q[(int64_t)(3 * Np + mm) * K + k];
+          p = sl.q[tix(4 * Np, mm, k)];
+          vx = sl.q[tix(4 * Np, Np + mm, k)];
+          vy = sl.q[tix(4 * Np, 2 * Np + mm, k)];
+          vz = sl.q[tix(4 * Np, 3 * Np + mm, k)];
         }
         short h, l;
         split_bf16(rx * vx + ry * vy + rz * vz, h, l); urh[v] = h; url[v] = l;
@@ -1215,7 +1036,7 @@ __global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) 
   float *tr = a.tr + (m & 1) * (int64_t)TRS * K;
   float g[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = a.geo[i * K + k];
+  for (int i = 0; i < 9; ++i) g[i] = a.geo[tix(kGeo, i, k)];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     float nx, ny, nz;
@@ -1228,10 +1049,10 @@ __global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) 
 #pragma unroll
     for (int i = 0; i < Nfp; ++i) {
       const int node = T.fmask[f][i];
-      const float p = a.q[(int64_t)node * K + k];
-      const float vx = a.q[(int64_t)(Np + node) * K + k];
-      const float vy = a.q[(int64_t)(2 * Np + node) * K + k];
-      const float vz = a.q[(int64_t)(3 * Np + node) * K + k];
+      const float p = a.q[tix(4 * Np, node, k)];
+      const float vx = a.q[tix(4 * Np, Np + node, k)];
+      const float vy = a.q[tix(4 * Np, 2 * Np + node, k)];
+      const float vz = a.q[tix(4 * Np, 3 * Np + node, k)];
       tr[(int64_t)k * TRS + f * FS + i] = p;
       tr[(int64_t)k * TRS + TRC + f * FS + i] = nx * vx + ny * vy + nz * vz;
     }
@@ -1249,7 +1070,7 @@ __global__ __launch_bounds__(256) void seg_init_kernel(const SegInitArgs a) {
   const int64_t kk = k - a.lev_begin[lev - 1];
   const int64_t Pl = level_end(a.lev_begin, a.L, lev) - a.lev_begin[lev - 1];
   const int64_t m0 = a.seg_m0[lev - 1];
-  const float zs = a.condition ? a.geo[11 * K + k] : 0.0f;
+  const float zs = a.condition ? a.geo[tix(kGeo, 11, k)] : 0.0f;
   const int64_t slab = (int64_t)4 * Np * K;
   for (int s = 1; s <= 2; ++s) {
     const int64_t ms = m0 - s;
@@ -1257,8 +1078,8 @@ __global__ __launch_bounds__(256) void seg_init_kernel(const SegInitArgs a) {
     for (int n = 0; n < Np; ++n) {
       float v = 0.0f;
       if (ms >= 0) {
-        const float r0 = R[(int64_t)n * K + k], r1 = R[(int64_t)(Np + n) * K + k];
-        const float r2 = R[(int64_t)(2 * Np + n) * K + k], r3 = R[(int64_t)(3 * Np + n) * K + k];
+        const float r0 = R[tix(4 * Np, n, k)], r1 = R[tix(4 * Np, Np + n, k)];
+        const float r2 = R[tix(4 * Np, 2 * Np + n, k)], r3 = R[tix(4 * Np, 3 * Np + n, k)];
         v = r0 - zs * (a.up[0] * r1 + a.up[1] * r2 + a.up[2] * r3);
       }
       a.seg_r[a.seg_r_off[lev - 1] + ((2 - s) * Np + n) * Pl + kk] = v;
@@ -1272,7 +1093,7 @@ __global__ void record_kernel(const float *q, int64_t K, const int64_t *pos, con
   if (r >= n_rec) return;
   const int64_t k = pos[r];
   float acc = 0.0f;
-  for (int n = 0; n < Np; ++n) acc += l[r * Np + n] * q[(int64_t)n * K + k];
+  for (int n = 0; n < Np; ++n) acc += l[r * Np + n] * q[tix(4 * Np, n, k)];
   out[r * stride] = acc;
 }
 
@@ -1281,7 +1102,7 @@ __global__ void to_dev_kernel(int Np, int nf, const float *user, float *dev, con
   if (t >= K * Np) return;
   const int64_t k = t % K, n = t / K;
   const int64_t u = s2u[k];
-  for (int c = 0; c < nf; ++c) dev[(c * Np + n) * K + k] = u >= 0 ? user[(u * nf + c) * Np + n] : 0.0f;
+  for (int c = 0; c < nf; ++c) dev[tix(nf * Np, c * Np + n, k)] = u >= 0 ? user[(u * nf + c) * Np + n] : 0.0f;
 }
 
 __global__ void to_user_kernel(int Np, int nf, const float *dev, float *user, const int64_t *s2u, int64_t K) {
@@ -1290,7 +1111,7 @@ __global__ void to_user_kernel(int Np, int nf, const float *dev, float *user, co
   const int64_t k = t % K, n = t / K;
   const int64_t u = s2u[k];
   if (u < 0) return;
-  for (int c = 0; c < nf; ++c) user[(u * nf + c) * Np + n] = dev[(c * Np + n) * K + k];
+  for (int c = 0; c < nf; ++c) user[(u * nf + c) * Np + n] = dev[tix(nf * Np, c * Np + n, k)];
 }
 
 __global__ void img_user_kernel(int Np, const double *img, double *user, const int64_t *s2u, int64_t K, int acc) {
@@ -1299,7 +1120,7 @@ __global__ void img_user_kernel(int Np, const double *img, double *user, const i
   const int64_t k = t % K, n = t / K;
   const int64_t u = s2u[k];
   if (u < 0) return;
-  const double v = img[n * K + k];
+  const double v = img[tix(Np, n, k)];
   if (acc) user[u * Np + n] += v;
   else user[u * Np + n] = v;
 }
@@ -1372,8 +1193,6 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
     }
     return hipGetLastError();
   }
-  constexpr size_t extra = (Dims<N>::TABW + 4 * Dims<N>::QT) * sizeof(float);
-  constexpr size_t lds = Dims<N>::OPS * sizeof(float) + extra;
   if constexpr (N >= 5) {
     constexpr size_t lds_lr = Dims<N>::OPS * sizeof(float);
     if constexpr (lds_lr <= 96 * 1024) {
@@ -1384,21 +1203,11 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
     } else {
       hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, false>), grid, block, 0, st, a);
     }
-  } else if constexpr (N <= 4) {
+  } else {
     // one work-group per CU (its static LDS fills the CU); each loops over tile groups
     const dim3 gridp((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
                      (unsigned)a.nslots);
     hipLaunchKernelGGL((step_kernel_dma<N, MODE>), gridp, block, 0, st, a);
-  } else if constexpr (lds <= 128 * 1024) {
-    static bool done = false;
-    hipError_t e = ensure_lds(step_kernel<N, MODE, true>, lds, done);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((step_kernel<N, MODE, true>), grid, block, lds, st, a);
-  } else {
-    static bool done = false;
-    hipError_t e = ensure_lds(step_kernel<N, MODE, false>, extra, done);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((step_kernel<N, MODE, false>), grid, block, extra, st, a);
   }
   return hipGetLastError();
 }
@@ -1416,7 +1225,7 @@ static hipError_t launch_step_n(const StepArgs &a, hipStream_t st) {
   }
 }
 
-// operator fragments in the MFMA A-operand lane order (see step_kernel)
+// operator fragments in the MFMA A-operand lane order (see step_kernel_dma)
 void build_op_fragments(int N, const float *Dr, const float *Ds, const float *Dt, const float *LIFT, float *out) {
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2, F = 4 * Nfp;
   const int NR = (Np + 15) / 16, NK = (Np + 3) / 4, FC = (Nfp + 3) / 4;

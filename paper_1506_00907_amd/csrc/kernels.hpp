@@ -1,14 +1,17 @@
 // Launch interface of the gfx950 DG kernels (FP32 state, FP64 image accumulation).
 //
-// Device layout (element index fastest, elements sorted finest level first, each level's
-// segment padded to a multiple of 64 so a wavefront never straddles two levels):
-//   q     [4][Np][Ktot]            p, vx, vy, vz
-//   ring  [3][4][Np][Ktot]         AB3 right-hand-side history, slot = own step index mod 3
+// Device layout (elements sorted finest level first, each level's segment padded to a multiple
+// of 64 so a wavefront never straddles two levels).  Per-element arrays of R rows are tiled:
+// element k's row r is at tix(R, r, k) = ((k / 16) R + r) 16 + k % 16, so a row of a 16-element
+// tile is 64 contiguous bytes and a tile's R rows are one contiguous block.
+//   q     [4 Np rows]              p, vx, vy, vz (row c Np + n)
+//   ring  [3][4 Np rows]           AB3 right-hand-side history, slot = own step index mod 3
 //   tr    [3][Ktot][2][4][FS]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step;
 //                                  face f's Nfp values start at f*FS, FS = Nfp rounded up to 4
-//   geo   [kGeo][Ktot]             rx ry rz sx sy sz tx ty tz, rho c^2, 1/rho, Z, tau_p[4], tau_v[4]
-//   nbr   [4][Ktot]                neighbour position, or -(boundary type) on a boundary face
-//   ncode [4][Ktot]                neighbour face | vertex permutation << 2 | neighbour level << 5
+//   geo   [kGeo rows]              rx ry rz sx sy sz tx ty tz, rho c^2, 1/rho, Z, tau_p[4], tau_v[4]
+//   nbr   [4 rows]                 neighbour position, or -(boundary type) on a boundary face
+//   ncode [4 rows]                 neighbour face | vertex permutation << 2 | neighbour level << 5
+//   img   [Np rows] (FP64)         image
 //   eflag [Ktot]                   bit0 real element, bit1 has a finer neighbour, bit2 has sources
 #pragma once
 #include <hip/hip_runtime.h>
@@ -23,6 +26,9 @@ constexpr int kMaxLevels = 8;
 enum StepMode : int { MODE_PLAIN = 0, MODE_RECORD_SEG = 1, MODE_IMAGE = 2, MODE_RHS_ONLY = 3 };
 
 constexpr int kMaxSlots = 8;
+
+// tiled index of row r of element k in an array with R rows per element
+__host__ __device__ constexpr int64_t tix(int64_t R, int64_t r, int64_t k) { return ((k >> 4) * R + r) * 16 + (k & 15); }
 
 // face stride of a trace row: Nfp rounded up to a multiple of 4 floats (16-byte aligned runs)
 __host__ __device__ constexpr int trace_face_stride(int Nfp) { return (Nfp + 3) & ~3; }
