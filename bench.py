@@ -64,7 +64,8 @@ def load_traffic(workload: str, mode_name: str):
     d = json.load(open(p))
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("modes", {}).get(mode_name)
+    m = d.get("modes", {}).get(mode_name)
+    return None if m is None else round(m["bytes_per_launch"], 1)
 
 
 def cpu_baseline(mesh_in, rho, c, N, n_levels, seconds_target=15.0):
@@ -128,6 +129,57 @@ def serving_bench(n_requests=12, t_final=0.05, meshes=("srv_50k", "srv_200k", "s
             "mix_vs_alone_max_rel_image_diff": worst_img, "mix_vs_alone_max_rel_trace_diff": worst_tr}
 
 
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_from_pmc(workload: str, fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
+                     command: str) -> str:
+    """HBM bytes per step-kernel launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
+    dispatch), each scaled by what the same counter reads for a device copy of known size, averaged
+    over the launches of each step mode like the roofline's achieved figure.  Writes the JSON that
+    the roofline's traffic field reads."""
+    import csv
+    import glob
+
+    def rows(d):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise FileNotFoundError(f"no counter_collection.csv under {d}")
+        return list(csv.DictReader(open(f[0])))
+
+    def copy_scale(d):
+        # the largest rocclr copy dispatch of the calibration run moved 2^30 bytes each way
+        r = [x for x in rows(d) if "copyBuffer" in x["Kernel_Name"]]
+        kib = max(float(x["Counter_Value"]) for x in r)
+        return (2 ** 30) / (kib * 1024.0), kib
+
+    sf, kf = copy_scale(copy_fetch_dir)
+    sw, kw = copy_scale(copy_write_dir)
+    names = {0: "forward_step", 1: "recompute_step", 2: "image_step"}
+    per = {}
+    for d, scale, key in ((fetch_dir, sf, "fetch"), (write_dir, sw, "write")):
+        for r in rows(d):
+            n = r["Kernel_Name"]
+            if "step_kernel" not in n:
+                continue
+            mode = int(n.split("<")[1].split(",")[1].split(">")[0])
+            per.setdefault(names.get(mode, str(mode)), {"fetch": [], "write": []})[key].append(
+                float(r["Counter_Value"]) * 1024.0 * scale)
+    modes = {m: {"fetch_bytes_per_launch": sum(v["fetch"]) / len(v["fetch"]),
+                 "write_bytes_per_launch": sum(v["write"]) / len(v["write"]),
+                 "bytes_per_launch": sum(v["fetch"]) / len(v["fetch"]) + sum(v["write"]) / len(v["write"]),
+                 "launches": len(v["fetch"])} for m, v in per.items() if v["fetch"] and v["write"]}
+    out = {"workload": workload, "kernel_source_sha256_16": kernel_source_hash(),
+           "copy_calibration": {"bytes": 2 ** 30, "FETCH_SIZE_KiB": kf, "WRITE_SIZE_KiB": kw,
+                                "fetch_scale": sf, "write_scale": sw},
+           "command": command, "modes": modes}
+    path = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    return path
+
+
 def _threads() -> int:
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         if os.environ.get(k):
@@ -146,7 +198,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=0, help="requests in the serving section (0 = skip)")
     ap.add_argument("--serving-t-final", type=float, default=0.05)
+    ap.add_argument("--traffic-from-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/step_kernel_<workload>_traffic.json from rocprofv3 --pmc output and exit")
+    ap.add_argument("--pmc-command", default="", help="the profiling command, recorded in the traffic JSON")
     args = ap.parse_args()
+    if args.traffic_from_pmc:
+        print(traffic_from_pmc(args.workload, *args.traffic_from_pmc, command=args.pmc_command))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the whole mesh and shot live on one MI355X "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
@@ -177,8 +235,13 @@ def main():
         shot.adjoint(traces, condition=dgrtm.IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start=0)
         shot.image(img)
 
-    for _ in range(args.warmup):
+    log(f"mesh {args.workload}: {mesh.K} elements, N={N}, {L} levels {list(map(int, hist))}, "
+        f"{ng} global steps per shot")
+    for i in range(args.warmup):
+        ts = time.perf_counter()
         one_shot()
+        torch.cuda.synchronize()
+        log(f"warm-up shot {i}: {time.perf_counter() - ts:.2f} s")
     torch.cuda.synchronize()
     shot.profile_start(args.sample_every)
     torch.cuda.synchronize()
@@ -189,6 +252,7 @@ def main():
         one_shot()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
+        log(f"timed shot {len(lat) - 1}: {lat[-1]:.2f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = {m: shot.profile_read(m) for m in (0, 1, 2)}
@@ -236,8 +300,10 @@ def main():
     }
     if args.serving > 0:
         del shot, traces, img
+        log(f"serving: {args.serving} requests ...")
         out["serving"] = serving_bench(args.serving, args.serving_t_final)
     if not args.no_cpu_baseline:
+        log("oracle CPU baseline sample ...")
         out["cpu_baseline"] = cpu_baseline(mm, rho, c, N, n_levels)
     print(json.dumps(out), flush=True)
 
