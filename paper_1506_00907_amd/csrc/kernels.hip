@@ -227,7 +227,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
                                           v4f (&rp)[Dims<N>::NR], v4f (&rvx)[Dims<N>::NR], v4f (&rvy)[Dims<N>::NR],
                                           v4f (&rvz)[Dims<N>::NR], float *sh1 = nullptr,
-                                          float *sh2 = nullptr) {
+                                          float *sh2 = nullptr, const float *sseg = nullptr) {
   constexpr Tab<N> T{};
   constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F, NR = Dims<N>::NR;
   const int64_t K = a.Ktot;
@@ -337,15 +337,27 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         if constexpr (QROW > 0) qo[i][c] = sq[(c * QROW + (ok ? n : 0)) * 16 + e];
         else qo[i][c] = ok ? q[idx] : 0.f;
       }
-      if constexpr (MODE == MODE_IMAGE) {
-        if (do_img && ok) {
-          const float *sqp = sl.seg_q + oq;
-          const float *srp = sl.seg_r + orr;
-          sqv[i] = sqp[(jS * Np + n) * Pl + kk];
-          srv[i][0] = srp[((jS + 2) * Np + n) * Pl + kk];
-          srv[i][1] = srp[((jS + 1) * Np + n) * Pl + kk];
-          srv[i][2] = srp[(jS * Np + n) * Pl + kk];
-          imv[i] = sl.img[tix(Np, n, k)];
+    }
+    if constexpr (MODE == MODE_IMAGE) {
+      if (do_img) {   // uniform over the tile; all loads of the row tile in one batch
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int n = 16 * rt + 4 * g + i;
+          const int nn = (16 * rt + 15 < Np || n < Np) ? n : 0;   // (rows past Np are not used)
+          if (sseg) {   // the tile's segment rows, already in LDS: [q][r(jS+2)][r(jS+1)][r(jS)] x Np x 16
+            sqv[i] = sseg[(0 * Np + nn) * 16 + e];
+            srv[i][0] = sseg[(1 * Np + nn) * 16 + e];
+            srv[i][1] = sseg[(2 * Np + nn) * 16 + e];
+            srv[i][2] = sseg[(3 * Np + nn) * 16 + e];
+          } else {
+            const float *sqp = sl.seg_q + oq;
+            const float *srp = sl.seg_r + orr;
+            sqv[i] = sqp[jS * Np * Pl + tix(Np, nn, kk)];
+            srv[i][0] = srp[(jS + 2) * Np * Pl + tix(Np, nn, kk)];
+            srv[i][1] = srp[(jS + 1) * Np * Pl + tix(Np, nn, kk)];
+            srv[i][2] = srp[jS * Np * Pl + tix(Np, nn, kk)];
+          }
+          imv[i] = sl.img[tix(Np, nn, k)];
         }
       }
     }
@@ -372,8 +384,8 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       if constexpr (MODE == MODE_RECORD_SEG) {
         const float qminus = qo[i][0] - zs * (ux * qo[i][1] + uy * qo[i][2] + uz * qo[i][3]);
         const float rminus = r[0] - zs * (ux * r[1] + uy * r[2] + uz * r[3]);
-        sl.seg_q[oq + (jS * Np + n) * Pl + kk] = qminus;
-        sl.seg_r[orr + ((jS + 2) * Np + n) * Pl + kk] = rminus;
+        sl.seg_q[oq + jS * Np * Pl + tix(Np, n, kk)] = qminus;
+        sl.seg_r[orr + (jS + 2) * Np * Pl + tix(Np, n, kk)] = rminus;
       }
       if constexpr (MODE == MODE_IMAGE) {
         if (do_img) {
@@ -541,7 +553,8 @@ struct DmaDims {
   static constexpr int NQ = (4 * Np + 15) / 16;      // 16-byte copies of a field tile
   static constexpr int NG = (kGeo + 15) / 16;        // ... of the geometry tile
   static constexpr int NT = 8;                       // 16-byte copies of the neighbour face runs
-  static constexpr int WAVE = QW + GW + TW + 2 * QW; // LDS floats per wavefront (history last)
+  static constexpr int EW = 4 * 16 + 4 * 16 + 16;    // element ids, codes and flags of a tile
+  static constexpr int WAVE = QW + GW + TW + 2 * QW + EW;  // LDS words per wavefront
 };
 
 template <int N, int MODE>
@@ -567,6 +580,9 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       for (int c = 0; c < NK; ++c) fD[j][rt][c] = a.ops[((j * NR + rt) * NK + c) * 64 + lane];
   stage_to_lds<NR * 4 * FC * 64>(a.ops + 3 * NR * NK * 64, sL);
   stage_to_lds<Dm::TABW>(a.nbr_index, stabw);
+  // all of the above has landed (a builtin wait, so that the compiler places no wait for the
+  // operator registers inside the tile loop, where it would also wait for the tile copies)
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const int8_t *stab = reinterpret_cast<const int8_t *>(stabw);
   const int64_t K = a.Ktot;
@@ -580,17 +596,25 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   float *const n_t = g_t + DD::GW;
   float *const h_t = n_t + DD::TW;
   const uint32_t lq = __builtin_amdgcn_readfirstlane(lds_addr(q_t));
-  const uint32_t lg = lq + 4 * QW, ln = lg + 4 * DD::GW, lh = ln + 4 * DD::TW;
+  const uint32_t lg = lq + 4 * QW, ln = lg + 4 * DD::GW, lh = ln + 4 * DD::TW, le = lh + 4 * 2 * QW;
+  const int *const e_t = reinterpret_cast<const int *>(h_t + 2 * QW);
 
   int nbv[4], codev[4], flag;
-  auto load_elem = [&](int64_t t, int (&nb)[4], int (&cd)[4], int &fl) {
-    const int64_t kk = t * 16 + e;
-    fl = sl.eflag[kk];
+  // element ids, codes and flags of a tile: three small LDS copies, read back when they have landed
+  auto issue_elem = [&](int64_t t) {
+    if (lane < 16) {
+      lds_copy16(a.nbr + tix(4, 0, t * 16) + 4 * lane, le);
+      lds_copy16(a.ncode + tix(4, 0, t * 16) + 4 * lane, le + 4 * 64);
+    }
+    if (lane < 4) lds_copy16(sl.eflag + t * 16 + 4 * lane, le + 4 * 128);
+  };
+  auto read_elem = [&](int (&nb)[4], int (&cd)[4], int &fl) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      nb[f] = a.nbr[tix(4, f, kk)];
-      cd[f] = a.ncode[tix(4, f, kk)];
+      nb[f] = e_t[f * 16 + e];
+      cd[f] = e_t[64 + f * 16 + e];
     }
+    fl = e_t[128 + e];
   };
   auto issue_tile = [&](int64_t t) {
     const int64_t k0 = t * 16;
@@ -619,8 +643,9 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       copy_block<4 * Np>(sl.ring + ((m + 1) % 3) * slab + tix(4 * Np, 0, k0), lh + 4 * QW, lane);
     }
   };
-  load_elem(tile, nbv, codev, flag);
-  asm volatile("" : "+v"(flag));   // consumed here, so no wait for it lands inside the loop
+  issue_elem(tile);
+  DGRTM_WAIT_VM(0);
+  read_elem(nbv, codev, flag);
   issue_tile(tile);
 
   while (true) {
@@ -638,8 +663,7 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     __builtin_amdgcn_sched_barrier(0);
     const int64_t k = tile * 16 + e;
     const int64_t nxt = tile + tstride;
-    int nbn[4], coden[4], flagn = 0;
-    if (nxt < ntiles) load_elem(nxt, nbn, coden, flagn);   // lands while this tile computes
+    if (nxt < ntiles) issue_elem(nxt);   // lands while this tile computes
     const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
     const int sh = a.L - lev;
     const int64_t m = sl.tau >> sh;
@@ -738,16 +762,33 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
           rvz[rt][i] -= nz * G[rt][i];
         }
     }
+    const float *sseg = nullptr;
+    if constexpr (MODE == MODE_IMAGE) {
+      // the source-wavefield segment rows this receiver step correlates with go to the geometry
+      // and neighbour-trace tiles, which the tile no longer reads
+      static_assert(4 * Np * 16 <= DD::GW + DD::TW, "segment rows fit in the geometry and trace tiles");
+      const int64_t mS = (sl.NG << (lev - 1)) - m - 1;
+      const int64_t jS = mS - (sl.g0 << (lev - 1));
+      if ((mS << sh) >= sl.image_from && jS >= 0 && jS < ((sl.g1 - sl.g0) << (lev - 1))) {
+        int64_t oq, orr;
+        seg_offsets(a, sl.C, Np, lev, oq, orr);
+        const int64_t Pl = level_end(a.lev_begin, a.L, lev) - a.lev_begin[lev - 1];
+        const int64_t kk0 = tile * 16 - a.lev_begin[lev - 1];
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the surface terms' LDS reads are done
+        copy_block<Np>(sl.seg_q + oq + jS * Np * Pl + tix(Np, 0, kk0), lg, lane);
+        copy_block<Np>(sl.seg_r + orr + (jS + 2) * Np * Pl + tix(Np, 0, kk0), lg + 4 * Np * 16, lane);
+        copy_block<Np>(sl.seg_r + orr + (jS + 1) * Np * Pl + tix(Np, 0, kk0), lg + 8 * Np * 16, lane);
+        copy_block<Np>(sl.seg_r + orr + jS * Np * Pl + tix(Np, 0, kk0), lg + 12 * Np * 16, lane);
+        sseg = g_t;
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
     DGRTM_WAIT_VM(0);   // the history copies (and the next tile's element data) have landed
     __builtin_amdgcn_sched_barrier(0);
-    // consume the next tile's element data now, while nothing else is in flight: a wait for it
-    // after the update's stores would also wait for those stores
-#pragma unroll
-    for (int f = 0; f < 4; ++f) asm volatile("" : "+v"(nbn[f]), "+v"(coden[f]));
-    asm volatile("" : "+v"(flagn));
+    int nbn[4], coden[4], flagn = 0;
+    if (nxt < ntiles) read_elem(nbn, coden, flagn);
     tile_tail<N, MODE, Np, HIST, HIST>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy,
-                                       rvz, h_t, h_t + QW);
+                                       rvz, h_t, h_t + QW, sseg);
     if constexpr (HIST) {
       tile_traces<N>(a, sl, k, g, e, m, flag, q_t, h_t + QW, nfx, nfy, nfz);
       // new state and new rhs of the tile: element-contiguous rows, 16 bytes per lane
@@ -1082,7 +1123,7 @@ __global__ __launch_bounds__(256) void seg_init_kernel(const SegInitArgs a) {
         const float r2 = R[tix(4 * Np, 2 * Np + n, k)], r3 = R[tix(4 * Np, 3 * Np + n, k)];
         v = r0 - zs * (a.up[0] * r1 + a.up[1] * r2 + a.up[2] * r3);
       }
-      a.seg_r[a.seg_r_off[lev - 1] + ((2 - s) * Np + n) * Pl + kk] = v;
+      a.seg_r[a.seg_r_off[lev - 1] + (2 - s) * Np * Pl + tix(Np, n, kk)] = v;
     }
   }
 }
