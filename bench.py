@@ -103,7 +103,11 @@ def serving_bench(n_requests=12, t_final=0.05, meshes=("srv_50k", "srv_200k", "s
     import copy
     import numpy as np
     from paper_1506_00907_amd import serving as S
-    pools = {m: S.MeshSlotPool(m) for m in meshes}
+    pools = {}
+    for m in meshes:
+        ts = time.perf_counter()
+        pools[m] = S.MeshSlotPool(m)
+        log(f"serving: mesh {m} bound in {time.perf_counter() - ts:.1f} s")
     # capacity of the sequential solver: one warm-up shot per mesh
     svc = []
     for m in meshes:
@@ -112,12 +116,15 @@ def serving_bench(n_requests=12, t_final=0.05, meshes=("srv_50k", "srv_200k", "s
         t0 = time.perf_counter()
         pools[m].run_alone(req)
         svc.append(time.perf_counter() - t0)
+        log(f"serving: one {m} shot alone takes {svc[-1]:.3f} s")
     capacity = 1.0 / float(np.mean(svc))
     rate = 1.2 * capacity
     reqs = S.make_requests(n_requests, rate, list(meshes), t_final, seed=seed)
     seq_res, bat_res = {}, {}
-    rs = S.serve_sequential(pools, copy.deepcopy(reqs), results=seq_res)
-    rb = S.serve_batched(pools, copy.deepcopy(reqs), hbm_budget, results=bat_res)
+    rs = S.serve_sequential(pools, copy.deepcopy(reqs), results=seq_res, log=log)
+    log(f"serving: one-at-a-time done in {rs.makespan:.2f} s")
+    rb = S.serve_batched(pools, copy.deepcopy(reqs), hbm_budget, results=bat_res, log=log)
+    log(f"serving: continuous batching done in {rb.makespan:.2f} s")
     worst_img, worst_tr = 0.0, 0.0
     for rid in seq_res:
         (ta, ia), (tb, ib) = seq_res[rid], bat_res[rid]
@@ -215,7 +222,10 @@ def main():
 
     from paper_1506_00907_amd import dgrtm, inputs as I
 
+    log(f"building the {args.workload} mesh ...")
+    ts = time.perf_counter()
     mm, rho, c, N = I.config_mesh(args.workload)
+    log(f"mesh generated: {mm.K} elements in {time.perf_counter() - ts:.1f} s; host set-up and upload ...")
     n_levels = 3
     mesh = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, n_levels).bind("cuda")
     spec = I.rtm_shot(box=mm.box, t_final=args.t_final)

@@ -133,8 +133,9 @@ class ServeResult:
 
 def serve_batched(pools: dict, requests: list[Request], hbm_budget: int, max_slots: int = 8,
                   steps_per_tick: int = 16, results: dict | None = None, clock=time.perf_counter,
-                  sleep=time.sleep) -> ServeResult:
-    """Continuous batching: admit as slots/memory free up; advance every running shot each tick."""
+                  sleep=time.sleep, log=None) -> ServeResult:
+    """Continuous batching: admit as slots/memory free up; advance every running shot each tick.
+    `log(msg)`, if given, is called when a request completes."""
     pending = sorted(requests, key=lambda r: r.arrival)
     waiting: list[Request] = []
     used = 0
@@ -179,6 +180,8 @@ def serve_batched(pools: dict, requests: list[Request], hbm_budget: int, max_slo
                         results[req.rid] = p.collect(shot)
                     used -= fp
                     done_count += 1
+                    if log is not None:
+                        log(f"request {req.rid} ({req.mesh}) done at {t_now:.3f} s")
                 else:
                     keep.append((req, shot, fp))
             p.running = keep
@@ -186,7 +189,7 @@ def serve_batched(pools: dict, requests: list[Request], hbm_budget: int, max_slo
 
 
 def serve_sequential(pools: dict, requests: list[Request], results: dict | None = None, clock=time.perf_counter,
-                     sleep=time.sleep) -> ServeResult:
+                     sleep=time.sleep, log=None) -> ServeResult:
     """Baseline: one shot at a time in arrival order, full forward + adjoint each."""
     t0 = clock()
     for req in sorted(requests, key=lambda r: r.arrival):
@@ -199,4 +202,6 @@ def serve_sequential(pools: dict, requests: list[Request], results: dict | None 
         req.done = clock() - t0
         if results is not None:
             results[req.rid] = out
+        if log is not None:
+            log(f"request {req.rid} ({req.mesh}) done at {req.done:.3f} s")
     return ServeResult(requests, clock() - t0)
