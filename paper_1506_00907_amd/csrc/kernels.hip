@@ -635,13 +635,16 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       }
       (void)perm;
     }
-    if constexpr (HIST) {
-      const int lev = level_of(a.lev_begin, a.L, k0);
-      const int64_t m = sl.tau >> (a.L - lev);
-      const int64_t slab = (int64_t)4 * Np * K;
-      copy_block<4 * Np>(sl.ring + ((m + 2) % 3) * slab + tix(4 * Np, 0, k0), lh, lane);
-      copy_block<4 * Np>(sl.ring + ((m + 1) % 3) * slab + tix(4 * Np, 0, k0), lh + 4 * QW, lane);
-    }
+  };
+  // the two older rhs of a tile: issued once the tile's fields have landed, so that they travel
+  // while the tile's operator products run instead of in the same burst as the fields
+  auto issue_hist = [&](int64_t t) {
+    const int64_t k0 = t * 16;
+    const int lev = level_of(a.lev_begin, a.L, k0);
+    const int64_t m = sl.tau >> (a.L - lev);
+    const int64_t slab = (int64_t)4 * Np * K;
+    copy_block<4 * Np>(sl.ring + ((m + 2) % 3) * slab + tix(4 * Np, 0, k0), lh, lane);
+    copy_block<4 * Np>(sl.ring + ((m + 1) % 3) * slab + tix(4 * Np, 0, k0), lh + 4 * QW, lane);
   };
   issue_elem(tile);
   DGRTM_WAIT_VM(0);
@@ -649,17 +652,11 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   issue_tile(tile);
 
   while (true) {
-    // fields, geometry and neighbour traces have landed; the history copies may be in flight
+    // the fields, geometry and neighbour traces of this tile have landed
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (HIST) {
-      static_assert(2 * DD::NQ == 18 || 2 * DD::NQ == 10 || 2 * DD::NQ == 6 || 2 * DD::NQ == 2, "history copies");
-      if constexpr (2 * DD::NQ == 18) DGRTM_WAIT_VM(18);
-      else if constexpr (2 * DD::NQ == 10) DGRTM_WAIT_VM(10);
-      else if constexpr (2 * DD::NQ == 6) DGRTM_WAIT_VM(6);
-      else DGRTM_WAIT_VM(2);
-    } else {
-      DGRTM_WAIT_VM(0);
-    }
+    DGRTM_WAIT_VM(0);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (HIST) issue_hist(tile);
     __builtin_amdgcn_sched_barrier(0);
     const int64_t k = tile * 16 + e;
     const int64_t nxt = tile + tstride;
