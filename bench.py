@@ -136,6 +136,13 @@ def serving_bench(n_requests=12, t_final=0.05, meshes=("srv_50k", "srv_200k", "s
             "mix_vs_alone_max_rel_image_diff": worst_img, "mix_vs_alone_max_rel_trace_diff": worst_tr}
 
 
+# LTS levels (at most), receiver grid (n x n) and source position of each benchmark shot
+SHOT_SHAPES = {
+    "default": {"levels": 3, "n_rec": 100},                               # the 200k-tet two-layer shot
+    "big_4m": {"levels": 4, "n_rec": 256, "src_xy": (5.0, 5.0)},         # the ~4M-tet 10 x 10 x 4 km shot
+}
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -226,9 +233,11 @@ def main():
     ts = time.perf_counter()
     mm, rho, c, N = I.config_mesh(args.workload)
     log(f"mesh generated: {mm.K} elements in {time.perf_counter() - ts:.1f} s; host set-up and upload ...")
-    n_levels = 3
+    shape = SHOT_SHAPES.get(args.workload, SHOT_SHAPES["default"])
+    n_levels = shape["levels"]
     mesh = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, n_levels).bind("cuda")
-    spec = I.rtm_shot(box=mm.box, t_final=args.t_final)
+    src_xy = shape.get("src_xy", (0.7797, 1.0))
+    spec = I.rtm_shot(box=mm.box, src_xy=src_xy, n_rec=shape["n_rec"], t_final=args.t_final)
     shot = dgrtm.Shot(mesh, dgrtm.ShotSpec(t_final=spec.t_final, src=spec.src, f_peak=spec.f_peak,
                                            t_peak=spec.t_peak, rec=spec.rec))
     lev = mesh.export_setup()["level"].astype(np.int64)

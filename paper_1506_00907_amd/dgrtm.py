@@ -76,6 +76,13 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     return lib
 
 
+# PyTorch provides the device memory and streams; its HIP runtime is brought in before the
+# library, so that one runtime serves both whatever order a caller imports them in.
+try:
+    import torch as _torch_first  # noqa: F401
+except ImportError:
+    pass
+
 _lib = load_library()
 
 
