@@ -344,7 +344,7 @@ static int64_t choose_interval(dgrtm_mesh m, const dgrtm_shot_args *a, int64_t n
   if (a->ckpt_interval > 0) return std::min(a->ckpt_interval, ng);
   const HostMesh &h = m->hm;
   const int Np = m->ref.Np;
-  double ck = 12.0 * Np * h.Ktot;
+  double ck = 3.0 * state_row(Np) * h.Ktot;
   double seg = 0;
   for (int l = 1; l <= h.L; ++l) seg += 2.0 * Np * (double)level_size_h(h, l) * (1 << (l - 1));
   int64_t C = (int64_t)std::llround(std::sqrt((double)ng * ck / std::max(seg, 1.0)));
@@ -357,12 +357,12 @@ static size_t shot_layout(dgrtm_shot sh, Bump &b) {
   const int Np = m->ref.Np, F = 4 * m->ref.Nfp;
   const int64_t K = h.Ktot;
   for (Field *f : {&sh->S, &sh->R}) {
-    f->q = b.take<float>((size_t)4 * Np * K);
-    f->ring = b.take<float>((size_t)12 * Np * K);
+    f->q = b.take<float>((size_t)state_row(Np) * K);
+    f->ring = b.take<float>((size_t)3 * state_row(Np) * K);
     f->tr = b.take<float>((size_t)3 * trace_row(m->ref.Nfp) * K);
   }
   sh->img = b.take<double>((size_t)Np * K);
-  sh->ckpt = b.take<float>((size_t)sh->n_ckpt * 12 * Np * K);
+  sh->ckpt = b.take<float>((size_t)sh->n_ckpt * 3 * state_row(Np) * K);
   int64_t oq = 0, orr = 0;
   for (int l = 1; l <= h.L; ++l) {
     const int64_t P = level_size_h(h, l), nst = sh->C * ((int64_t)1 << (l - 1));
@@ -578,8 +578,8 @@ static dgrtm_status zero_field(dgrtm_shot sh, Field &f) {
   dgrtm_mesh m = sh->mesh;
   const int Np = m->ref.Np, F = 4 * m->ref.Nfp;
   const int64_t K = m->hm.Ktot;
-  HIPCHK(launch_fill_f32(f.q, 4LL * Np * K, 0.0f, m->stream));
-  HIPCHK(launch_fill_f32(f.ring, 12LL * Np * K, 0.0f, m->stream));
+  HIPCHK(launch_fill_f32(f.q, (int64_t)state_row(Np) * K, 0.0f, m->stream));
+  HIPCHK(launch_fill_f32(f.ring, 3LL * state_row(Np) * K, 0.0f, m->stream));
   HIPCHK(launch_fill_f32(f.tr, 3LL * trace_row(m->ref.Nfp) * K, 0.0f, m->stream));
   f.tau = 0;
   return DGRTM_OK;
@@ -712,7 +712,7 @@ static dgrtm_status ckpt_copy(dgrtm_shot sh, Field &f, int64_t c, bool save) {
   dgrtm_mesh m = sh->mesh;
   const HostMesh &h = m->hm;
   const int Np = m->ref.Np;
-  const int64_t K = h.Ktot, slab = 4LL * Np * K;
+  const int64_t K = h.Ktot, slab = (int64_t)state_row(Np) * K;
   float *ck = sh->ckpt + c * 3 * slab;
   const int64_t g = c * sh->C;
   hipStream_t st = m->stream;
@@ -725,9 +725,9 @@ static dgrtm_status ckpt_copy(dgrtm_shot sh, Field &f, int64_t c, bool save) {
     for (int s = 1; s <= 2; ++s) {
       // a level is a whole number of tiles, hence one contiguous block of the tiled layout
       const int64_t slot = ((mstep - s) % 3 + 3) % 3;
-      float *ring = f.ring + slot * slab + tix(4 * Np, 0, b0);
-      float *cks = ck + s * slab + tix(4 * Np, 0, b0);
-      const size_t bytes = (size_t)P * 4 * Np * sizeof(float);
+      float *ring = f.ring + slot * slab + b0 * state_row(Np);
+      float *cks = ck + s * slab + b0 * state_row(Np);
+      const size_t bytes = (size_t)P * state_row(Np) * sizeof(float);
       if (save) HIPCHK(hipMemcpyAsync(cks, ring, bytes, hipMemcpyDeviceToDevice, st));
       else HIPCHK(hipMemcpyAsync(ring, cks, bytes, hipMemcpyDeviceToDevice, st));
     }
@@ -1018,7 +1018,7 @@ extern "C" dgrtm_status dgrtm_set_state(dgrtm_shot sh, int which, const float *q
   if (!sh || (which != 0 && which != 1)) return fail(DGRTM_ERR_ARG, "dgrtm_set_state: bad argument");
   dgrtm_mesh m = sh->mesh;
   const int Np = m->ref.Np;
-  const int64_t K = m->hm.Ktot, slab = 4LL * Np * K;
+  const int64_t K = m->hm.Ktot, slab = (int64_t)state_row(Np) * K;
   Field &f = which ? sh->R : sh->S;
   dgrtm_status s;
   if ((s = zero_field(sh, f))) return s;

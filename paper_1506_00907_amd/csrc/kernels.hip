@@ -66,6 +66,12 @@ struct Dims {
   static constexpr int TRS = 2 * TRC;                             // element stride (floats)
 };
 
+// index of field c, node n of tile element e in an LDS copy of a tile's state (quad layout)
+template <int N>
+__device__ __forceinline__ constexpr int lqix(int c, int n, int e) {
+  return ((c * Dims<N>::NK + (n >> 2)) * 16 + e) * 4 + (n & 3);
+}
+
 // AB3 weights of the full step and of the half step, image weights for the mixed-direction
 // correlation (S forward from t_a, R backward from t_b): ebar_s = int_0^1 A_s,
 // Cmix_{s1 s2} = int_0^1 A_s1(th) A_s2(1-th), with A_s = int_0^th of the Lagrange basis on {0,-1,-2}
@@ -178,9 +184,9 @@ __device__ __forceinline__ void penalty(const StepArgs &a, const float *q, const
                                         float rc2, float irho, float &mPp, float &Pv) {
   constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F;
   const int64_t K = a.Ktot;
-  const float pm = q[tix(4 * Np, node, k)];
-  const float nvm = c.nx * q[tix(4 * Np, Np + node, k)] + c.ny * q[tix(4 * Np, 2 * Np + node, k)] +
-                    c.nz * q[tix(4 * Np, 3 * Np + node, k)];
+  constexpr int NQ4 = node_quads(Np);
+  const float pm = q[qix(NQ4, 0, node, k)];
+  const float nvm = c.nx * q[qix(NQ4, 1, node, k)] + c.ny * q[qix(NQ4, 2, node, k)] + c.nz * q[qix(NQ4, 3, node, k)];
   float pp, nvp;
   if (c.nb >= 0) {
     const float *nbt = c.trp + (int64_t)c.nb * Dims<N>::TRS + c.f2 * Dims<N>::FS + c.tab[s];
@@ -216,12 +222,12 @@ __device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np
   }
 }
 
-// QROW > 0: the old state comes from an LDS tile [4 QROW][16] (field c, node n at row c QROW + n)
-// instead of global memory; HLDS: the two older rhs come from LDS tiles [4 Np][16] (sh1, sh2).
+// QLDS: the old state comes from an LDS tile in the quad layout (field c, node n of element e at
+// lqix(c, n, e)) instead of global memory; HLDS: the two older rhs come from LDS tiles (sh1, sh2).
 // TR2 (needs both): no per-lane stores of the state, the rhs or the traces; the new state replaces
 // the old one in sq, the new rhs the first older rhs in sh1 and the half-step state the second in
 // sh2, for tile_traces and store_rows to write out with 16-byte stores.
-template <int N, int MODE, int QROW = 0, bool HLDS = false, bool TR2 = false>
+template <int N, int MODE, bool QLDS = false, bool HLDS = false, bool TR2 = false>
 __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
                                           int64_t m, int flag, float *sq, int e,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
@@ -231,6 +237,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
   constexpr Tab<N> T{};
   constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F, NR = Dims<N>::NR;
   const int64_t K = a.Ktot;
+  constexpr int NQ4 = node_quads(Np);
   const bool valid = (flag & 1) != 0;
   if (a.out_sign < 0.0f) {
 #pragma unroll
@@ -277,15 +284,15 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       for (int i = 0; i < 4; ++i) {
         const int n = 16 * rt + 4 * g + i;
         if (16 * rt + 15 < Np || n < Np) {
-          sl.rhs_out[tix(4 * Np, 0 * Np + n, k)] = rp[rt][i];
-          sl.rhs_out[tix(4 * Np, 1 * Np + n, k)] = rvx[rt][i];
-          sl.rhs_out[tix(4 * Np, 2 * Np + n, k)] = rvy[rt][i];
-          sl.rhs_out[tix(4 * Np, 3 * Np + n, k)] = rvz[rt][i];
+          sl.rhs_out[qix(NQ4, 0, n, k)] = rp[rt][i];
+          sl.rhs_out[qix(NQ4, 1, n, k)] = rvx[rt][i];
+          sl.rhs_out[qix(NQ4, 2, n, k)] = rvy[rt][i];
+          sl.rhs_out[qix(NQ4, 3, n, k)] = rvz[rt][i];
         }
       }
     return;
   }
-  const int64_t slab = (int64_t)4 * Np * K;
+  const int64_t slab = (int64_t)state_row(Np) * K;
   const float dtl = (float)(a.dt_local * (double)(1LL << sh));
   float *__restrict__ R0 = sl.ring + (m % 3) * slab;
   const float *__restrict__ R1 = sl.ring + ((m + 2) % 3) * slab;
@@ -326,15 +333,15 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       const bool ok = (16 * rt + 15 < Np || n < Np);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int64_t idx = tix(4 * Np, c * Np + (ok ? n : 0), k);
+        const int64_t idx = qix(NQ4, c, ok ? n : 0, k);
         if constexpr (HLDS) {
-          h1[i][c] = sh1[(c * Np + (ok ? n : 0)) * 16 + e];
-          h2[i][c] = sh2[(c * Np + (ok ? n : 0)) * 16 + e];
+          h1[i][c] = sh1[lqix<N>(c, ok ? n : 0, e)];
+          h2[i][c] = sh2[lqix<N>(c, ok ? n : 0, e)];
         } else {
           h1[i][c] = ok ? R1[idx] : 0.f;
           h2[i][c] = ok ? R2[idx] : 0.f;
         }
-        if constexpr (QROW > 0) qo[i][c] = sq[(c * QROW + (ok ? n : 0)) * 16 + e];
+        if constexpr (QLDS) qo[i][c] = sq[lqix<N>(c, ok ? n : 0, e)];
         else qo[i][c] = ok ? q[idx] : 0.f;
       }
     }
@@ -369,13 +376,13 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       float qn[4], qm[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int64_t idx = tix(4 * Np, c * Np + n, k);
+        const int64_t idx = qix(NQ4, c, n, k);
         qn[c] = qo[i][c] + dtl * (kA0 * r[c] + kA1 * h1[i][c] + kA2 * h2[i][c]);
         qm[c] = qo[i][c] + dtl * (kB0 * r[c] + kB1 * h1[i][c] + kB2 * h2[i][c]);
         if constexpr (TR2) {   // (these slots were read above and are not read again)
-          sq[(c * QROW + n) * 16 + e] = qn[c];
-          sh1[(c * Np + n) * 16 + e] = r[c];
-          sh2[(c * Np + n) * 16 + e] = qm[c];
+          sq[lqix<N>(c, n, e)] = qn[c];
+          sh1[lqix<N>(c, n, e)] = r[c];
+          sh2[lqix<N>(c, n, e)] = qm[c];
         } else {
           R0[idx] = r[c];
           q[idx] = qn[c];
@@ -452,10 +459,10 @@ __device__ __forceinline__ void tile_traces(const StepArgs &a, const SlotArgs &s
       p[u] = v[u] = pm[u] = vm[u] = 0.0f;
       if (s < Nfp) {
         const int node = sel4(g, T.fmask[0][s], T.fmask[1][s], T.fmask[2][s], T.fmask[3][s]);
-        p[u] = sq[node * 16 + e];
-        v[u] = nx * sq[(Np + node) * 16 + e] + ny * sq[(2 * Np + node) * 16 + e] + nz * sq[(3 * Np + node) * 16 + e];
-        pm[u] = sqm[node * 16 + e];
-        vm[u] = nx * sqm[(Np + node) * 16 + e] + ny * sqm[(2 * Np + node) * 16 + e] + nz * sqm[(3 * Np + node) * 16 + e];
+        p[u] = sq[lqix<N>(0, node, e)];
+        v[u] = nx * sq[lqix<N>(1, node, e)] + ny * sq[lqix<N>(2, node, e)] + nz * sq[lqix<N>(3, node, e)];
+        pm[u] = sqm[lqix<N>(0, node, e)];
+        vm[u] = nx * sqm[lqix<N>(1, node, e)] + ny * sqm[lqix<N>(2, node, e)] + nz * sqm[lqix<N>(3, node, e)];
       }
     }
     *reinterpret_cast<float4 *>(trw + 4 * j) = float4{p[0], p[1], p[2], p[3]};
@@ -546,15 +553,14 @@ __device__ __forceinline__ void store_block(const float *lds, float *dst, int la
 template <int N>
 struct DmaDims {
   static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, FC = Dims<N>::FC;
-  static constexpr int QW = 4 * Np * 16;             // floats of one wavefront's field tile
+  static constexpr int QW = 4 * Dims<N>::NK * 64;    // floats of one tile's state (quad layout)
   static constexpr int GW = kGeo * 16;               // geometry tile
   static constexpr int FS = Dims<N>::FS;
   static constexpr int TW = 8 * 16 * FS;             // neighbour face runs [face][p, n.v][FS/4][16][4]
-  static constexpr int NQ = (4 * Np + 15) / 16;      // 16-byte copies of a field tile
+  static constexpr int NQ = QW / 256;                // 1 KB copies of a tile's state
   static constexpr int NG = (kGeo + 15) / 16;        // ... of the geometry tile
   static constexpr int NT = 8;                       // 16-byte copies of the neighbour face runs
-  static constexpr int EW = 4 * 16 + 4 * 16 + 16;    // element ids, codes and flags of a tile
-  static constexpr int WAVE = QW + GW + TW + 2 * QW + EW;  // LDS words per wavefront
+  static constexpr int WAVE = QW + GW + TW + 2 * QW;  // LDS words per wavefront
 };
 
 template <int N, int MODE>
@@ -596,29 +602,23 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   float *const n_t = g_t + DD::GW;
   float *const h_t = n_t + DD::TW;
   const uint32_t lq = __builtin_amdgcn_readfirstlane(lds_addr(q_t));
-  const uint32_t lg = lq + 4 * QW, ln = lg + 4 * DD::GW, lh = ln + 4 * DD::TW, le = lh + 4 * 2 * QW;
-  const int *const e_t = reinterpret_cast<const int *>(h_t + 2 * QW);
+  const uint32_t lg = lq + 4 * QW, ln = lg + 4 * DD::GW, lh = ln + 4 * DD::TW;
 
   int nbv[4], codev[4], flag;
-  // element ids, codes and flags of a tile: three small LDS copies, read back when they have landed
-  auto issue_elem = [&](int64_t t) {
-    if (lane < 16) {
-      lds_copy16(a.nbr + tix(4, 0, t * 16) + 4 * lane, le);
-      lds_copy16(a.ncode + tix(4, 0, t * 16) + 4 * lane, le + 4 * 64);
-    }
-    if (lane < 4) lds_copy16(sl.eflag + t * 16 + 4 * lane, le + 4 * 128);
-  };
-  auto read_elem = [&](int (&nb)[4], int (&cd)[4], int &fl) {
+  // element ids, codes and flags of a tile (registers; the tile loop reads them only after an
+  // explicit wait, so they are marked consumed there and the compiler places no wait of its own)
+  auto load_elem = [&](int64_t t, int (&nb)[4], int (&cd)[4], int &fl) {
+    const int64_t kk = t * 16 + e;
+    fl = sl.eflag[kk];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      nb[f] = e_t[f * 16 + e];
-      cd[f] = e_t[64 + f * 16 + e];
+      nb[f] = a.nbr[tix(4, f, kk)];
+      cd[f] = a.ncode[tix(4, f, kk)];
     }
-    fl = e_t[128 + e];
   };
   auto issue_tile = [&](int64_t t) {
     const int64_t k0 = t * 16;
-    copy_block<4 * Np>(sl.q + tix(4 * Np, 0, k0), lq, lane);
+    copy_block<16 * NK>(sl.q + (k0 >> 4) * QW, lq, lane);
     copy_block<kGeo>(a.geo + tix(kGeo, 0, k0), lg, lane);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -642,13 +642,14 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     const int64_t k0 = t * 16;
     const int lev = level_of(a.lev_begin, a.L, k0);
     const int64_t m = sl.tau >> (a.L - lev);
-    const int64_t slab = (int64_t)4 * Np * K;
-    copy_block<4 * Np>(sl.ring + ((m + 2) % 3) * slab + tix(4 * Np, 0, k0), lh, lane);
-    copy_block<4 * Np>(sl.ring + ((m + 1) % 3) * slab + tix(4 * Np, 0, k0), lh + 4 * QW, lane);
+    const int64_t slab = (int64_t)state_row(Np) * K;
+    copy_block<16 * NK>(sl.ring + ((m + 2) % 3) * slab + (k0 >> 4) * QW, lh, lane);
+    copy_block<16 * NK>(sl.ring + ((m + 1) % 3) * slab + (k0 >> 4) * QW, lh + 4 * QW, lane);
   };
-  issue_elem(tile);
-  DGRTM_WAIT_VM(0);
-  read_elem(nbv, codev, flag);
+  load_elem(tile, nbv, codev, flag);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) asm volatile("" : "+v"(nbv[f]), "+v"(codev[f]));
+  asm volatile("" : "+v"(flag));
   issue_tile(tile);
 
   while (true) {
@@ -660,7 +661,8 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     __builtin_amdgcn_sched_barrier(0);
     const int64_t k = tile * 16 + e;
     const int64_t nxt = tile + tstride;
-    if (nxt < ntiles) issue_elem(nxt);   // lands while this tile computes
+    int nbn[4], coden[4], flagn = 0;
+    if (nxt < ntiles) load_elem(nxt, nbn, coden, flagn);   // lands while this tile computes
     const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
     const int sh = a.L - lev;
     const int64_t m = sl.tau >> sh;
@@ -681,10 +683,10 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       const int mm = 4 * c + g;
       const bool ok = 4 * c + 3 < Np || mm < Np;
       const int mr = ok ? mm : 0;
-      const float p = ok ? q_t[mr * 16 + e] : 0.f;
-      const float vx = ok ? q_t[(Np + mr) * 16 + e] : 0.f;
-      const float vy = ok ? q_t[(2 * Np + mr) * 16 + e] : 0.f;
-      const float vz = ok ? q_t[(3 * Np + mr) * 16 + e] : 0.f;
+      const float p = ok ? q_t[lqix<N>(0, mr, e)] : 0.f;
+      const float vx = ok ? q_t[lqix<N>(1, mr, e)] : 0.f;
+      const float vy = ok ? q_t[lqix<N>(2, mr, e)] : 0.f;
+      const float vz = ok ? q_t[lqix<N>(3, mr, e)] : 0.f;
       const float Ur = rx * vx + ry * vy + rz * vz;
       const float Us = sx * vx + sy * vy + sz * vz;
       const float Ut = tx * vx + ty * vy + tz * vz;
@@ -730,9 +732,8 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
         const bool sv = 4 * cc + 3 < Nfp || 4 * cc + g < Nfp;   // face node 4 cc + g exists
         const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
                               T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
-        const float pm = q_t[node * 16 + e];
-        const float nvm = nx * q_t[(Np + node) * 16 + e] + ny * q_t[(2 * Np + node) * 16 + e] +
-                          nz * q_t[(3 * Np + node) * 16 + e];
+        const float pm = q_t[lqix<N>(0, node, e)];
+        const float nvm = nx * q_t[lqix<N>(1, node, e)] + ny * q_t[lqix<N>(2, node, e)] + nz * q_t[lqix<N>(3, node, e)];
         // the neighbour's node matching face node 4 cc + g of this face
         const int t = stab[((f * 4 + f2) * 6 + perm) * Nfp + min(4 * cc + g, Nfp - 1)];
         const int toff = (t >> 2) * 64 + e * 4 + (t & 3);
@@ -782,16 +783,17 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     __builtin_amdgcn_sched_barrier(0);
     DGRTM_WAIT_VM(0);   // the history copies (and the next tile's element data) have landed
     __builtin_amdgcn_sched_barrier(0);
-    int nbn[4], coden[4], flagn = 0;
-    if (nxt < ntiles) read_elem(nbn, coden, flagn);
-    tile_tail<N, MODE, Np, HIST, HIST>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy,
+#pragma unroll
+    for (int f = 0; f < 4; ++f) asm volatile("" : "+v"(nbn[f]), "+v"(coden[f]));
+    asm volatile("" : "+v"(flagn));
+    tile_tail<N, MODE, true, HIST, HIST>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy,
                                        rvz, h_t, h_t + QW, sseg);
     if constexpr (HIST) {
       tile_traces<N>(a, sl, k, g, e, m, flag, q_t, h_t + QW, nfx, nfy, nfz);
       // new state and new rhs of the tile: element-contiguous rows, 16 bytes per lane
       const int64_t k0 = tile * 16;
-      store_block<4 * Np>(q_t, sl.q + tix(4 * Np, 0, k0), lane);
-      store_block<4 * Np>(h_t, sl.ring + (m % 3) * ((int64_t)4 * Np * K) + tix(4 * Np, 0, k0), lane);
+      store_block<16 * NK>(q_t, sl.q + (k0 >> 4) * QW, lane);
+      store_block<16 * NK>(h_t, sl.ring + (m % 3) * ((int64_t)state_row(Np) * K) + (k0 >> 4) * QW, lane);
     }
     if (nxt >= ntiles) break;
     // every LDS access of this tile has completed before the next tile's copies may land
@@ -860,10 +862,10 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       const int mm = 4 * c + g;
       float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
       if (mm < Np) {
-        p = sl.q[tix(4 * Np, mm, k)];
-        vx = sl.q[tix(4 * Np, Np + mm, k)];
-        vy = sl.q[tix(4 * Np, 2 * Np + mm, k)];
-        vz = sl.q[tix(4 * Np, 3 * Np + mm, k)];
+        p = sl.q[qix(node_quads(Np), 0, mm, k)];
+        vx = sl.q[qix(node_quads(Np), 1, mm, k)];
+        vy = sl.q[qix(node_quads(Np), 2, mm, k)];
+        vz = sl.q[qix(node_quads(Np), 3, mm, k)];
       }
       const float Ur = rx * vx + ry * vy + rz * vz;
       const float Us = sx * vx + sy * vy + sz * vz;
@@ -986,10 +988,10 @@ __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
         const int mm = 16 * c + 4 * g + v;
         float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
         if (mm < Np) {
-          p = sl.q[tix(4 * Np, mm, k)];
-          vx = sl.q[tix(4 * Np, Np + mm, k)];
-          vy = sl.q[tix(4 * Np, 2 * Np + mm, k)];
-          vz = sl.q[tix(4 * Np, 3 * Np + mm, k)];
+          p = sl.q[qix(node_quads(Np), 0, mm, k)];
+          vx = sl.q[qix(node_quads(Np), 1, mm, k)];
+          vy = sl.q[qix(node_quads(Np), 2, mm, k)];
+          vz = sl.q[qix(node_quads(Np), 3, mm, k)];
         }
         short h, l;
         split_bf16(rx * vx + ry * vy + rz * vz, h, l); urh[v] = h; url[v] = l;
@@ -1087,10 +1089,10 @@ __global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) 
 #pragma unroll
     for (int i = 0; i < Nfp; ++i) {
       const int node = T.fmask[f][i];
-      const float p = a.q[tix(4 * Np, node, k)];
-      const float vx = a.q[tix(4 * Np, Np + node, k)];
-      const float vy = a.q[tix(4 * Np, 2 * Np + node, k)];
-      const float vz = a.q[tix(4 * Np, 3 * Np + node, k)];
+      const float p = a.q[qix(node_quads(Np), 0, node, k)];
+      const float vx = a.q[qix(node_quads(Np), 1, node, k)];
+      const float vy = a.q[qix(node_quads(Np), 2, node, k)];
+      const float vz = a.q[qix(node_quads(Np), 3, node, k)];
       tr[(int64_t)k * TRS + f * FS + i] = p;
       tr[(int64_t)k * TRS + TRC + f * FS + i] = nx * vx + ny * vy + nz * vz;
     }
@@ -1109,15 +1111,15 @@ __global__ __launch_bounds__(256) void seg_init_kernel(const SegInitArgs a) {
   const int64_t Pl = level_end(a.lev_begin, a.L, lev) - a.lev_begin[lev - 1];
   const int64_t m0 = a.seg_m0[lev - 1];
   const float zs = a.condition ? a.geo[tix(kGeo, 11, k)] : 0.0f;
-  const int64_t slab = (int64_t)4 * Np * K;
+  const int64_t slab = (int64_t)state_row(Np) * K;
   for (int s = 1; s <= 2; ++s) {
     const int64_t ms = m0 - s;
     const float *R = a.ring + ((ms % 3 + 3) % 3) * slab;
     for (int n = 0; n < Np; ++n) {
       float v = 0.0f;
       if (ms >= 0) {
-        const float r0 = R[tix(4 * Np, n, k)], r1 = R[tix(4 * Np, Np + n, k)];
-        const float r2 = R[tix(4 * Np, 2 * Np + n, k)], r3 = R[tix(4 * Np, 3 * Np + n, k)];
+        const float r0 = R[qix(node_quads(Np), 0, n, k)], r1 = R[qix(node_quads(Np), 1, n, k)];
+        const float r2 = R[qix(node_quads(Np), 2, n, k)], r3 = R[qix(node_quads(Np), 3, n, k)];
         v = r0 - zs * (a.up[0] * r1 + a.up[1] * r2 + a.up[2] * r3);
       }
       a.seg_r[a.seg_r_off[lev - 1] + (2 - s) * Np * Pl + tix(Np, n, kk)] = v;
@@ -1131,7 +1133,7 @@ __global__ void record_kernel(const float *q, int64_t K, const int64_t *pos, con
   if (r >= n_rec) return;
   const int64_t k = pos[r];
   float acc = 0.0f;
-  for (int n = 0; n < Np; ++n) acc += l[r * Np + n] * q[tix(4 * Np, n, k)];
+  for (int n = 0; n < Np; ++n) acc += l[r * Np + n] * q[qix(node_quads(Np), 0, n, k)];
   out[r * stride] = acc;
 }
 
@@ -1140,7 +1142,7 @@ __global__ void to_dev_kernel(int Np, int nf, const float *user, float *dev, con
   if (t >= K * Np) return;
   const int64_t k = t % K, n = t / K;
   const int64_t u = s2u[k];
-  for (int c = 0; c < nf; ++c) dev[tix(nf * Np, c * Np + n, k)] = u >= 0 ? user[(u * nf + c) * Np + n] : 0.0f;
+  for (int c = 0; c < nf; ++c) dev[qix(node_quads(Np), c, n, k)] = u >= 0 ? user[(u * nf + c) * Np + n] : 0.0f;
 }
 
 __global__ void to_user_kernel(int Np, int nf, const float *dev, float *user, const int64_t *s2u, int64_t K) {
@@ -1149,7 +1151,7 @@ __global__ void to_user_kernel(int Np, int nf, const float *dev, float *user, co
   const int64_t k = t % K, n = t / K;
   const int64_t u = s2u[k];
   if (u < 0) return;
-  for (int c = 0; c < nf; ++c) user[(u * nf + c) * Np + n] = dev[tix(nf * Np, c * Np + n, k)];
+  for (int c = 0; c < nf; ++c) user[(u * nf + c) * Np + n] = dev[qix(node_quads(Np), c, n, k)];
 }
 
 __global__ void img_user_kernel(int Np, const double *img, double *user, const int64_t *s2u, int64_t K, int acc) {
@@ -1404,11 +1406,13 @@ hipError_t launch_record(int N, const float *q, int64_t Ktot, const int64_t *rec
 
 hipError_t launch_to_device_layout(int Np, int nf, const float *user, float *dev, const int64_t *s2u, int64_t K,
                                    hipStream_t st) {
+  if (nf != 4) return hipErrorInvalidValue;   // the quad layout holds the four fields
   hipLaunchKernelGGL(to_dev_kernel, dim3(blocks_for(K * Np, 256)), dim3(256), 0, st, Np, nf, user, dev, s2u, K);
   return hipGetLastError();
 }
 hipError_t launch_to_user_layout(int Np, int nf, const float *dev, float *user, const int64_t *s2u, int64_t K,
                                  hipStream_t st) {
+  if (nf != 4) return hipErrorInvalidValue;   // the quad layout holds the four fields
   hipLaunchKernelGGL(to_user_kernel, dim3(blocks_for(K * Np, 256)), dim3(256), 0, st, Np, nf, dev, user, s2u, K);
   return hipGetLastError();
 }

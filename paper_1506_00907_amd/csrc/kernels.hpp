@@ -4,8 +4,8 @@
 // of 64 so a wavefront never straddles two levels).  Per-element arrays of R rows are tiled:
 // element k's row r is at tix(R, r, k) = ((k / 16) R + r) 16 + k % 16, so a row of a 16-element
 // tile is 64 contiguous bytes and a tile's R rows are one contiguous block.
-//   q     [4 Np rows]              p, vx, vy, vz (row c Np + n)
-//   ring  [3][4 Np rows]           AB3 right-hand-side history, slot = own step index mod 3
+//   q     quad layout, qix()       p, vx, vy, vz
+//   ring  [3] x quad layout        AB3 right-hand-side history, slot = own step index mod 3
 //   tr    [3][Ktot][2][4][FS]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step;
 //                                  face f's Nfp values start at f*FS, FS = Nfp rounded up to 4
 //   geo   [kGeo rows]              rx ry rz sx sy sz tx ty tz, rho c^2, 1/rho, Z, tau_p[4], tau_v[4]
@@ -26,6 +26,18 @@ constexpr int kMaxLevels = 8;
 enum StepMode : int { MODE_PLAIN = 0, MODE_RECORD_SEG = 1, MODE_IMAGE = 2, MODE_RHS_ONLY = 3 };
 
 constexpr int kMaxSlots = 8;
+
+// Quad layout of the state and of each rhs of the ring: field c, node n of element k at
+// qix(NK, c, n, k), NK = ceil(Np / 4) node quads per field.  A tile's state is one block of
+// 4 NK 64 floats; within it, one node quad of one field is 64 floats, element-major with the quad's
+// 4 nodes adjacent.  A lane that owns element e and nodes 4 q .. 4 q + 3 (the MFMA C layout) reads
+// them with one 16-byte access, and the 64 lanes reading node 4 c + g of element e for g = 0..3
+// (the MFMA B layout) read 256 contiguous bytes.  The padding nodes of the last quad hold zeros.
+__host__ __device__ constexpr int node_quads(int Np) { return (Np + 3) / 4; }
+__host__ __device__ constexpr int state_row(int Np) { return 16 * node_quads(Np); }   // floats per element
+__host__ __device__ constexpr int64_t qix(int NK, int c, int n, int64_t k) {
+  return ((((k >> 4) * 4 + c) * NK + (n >> 2)) * 16 + (k & 15)) * 4 + (n & 3);
+}
 
 // tiled index of row r of element k in an array with R rows per element
 __host__ __device__ constexpr int64_t tix(int64_t R, int64_t r, int64_t k) { return ((k >> 4) * R + r) * 16 + (k & 15); }
