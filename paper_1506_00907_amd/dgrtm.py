@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from contextlib import contextmanager
 from dataclasses import dataclass
 
 import numpy as np
@@ -104,6 +105,28 @@ def _torch():
     return torch
 
 
+@contextmanager
+def _ordered(mesh, *inputs):
+    """Run library calls on the mesh's stream, ordered against the caller's current stream.
+
+    On entry the mesh stream waits for the work already queued on the caller's stream (the
+    producers of `inputs` and of freshly allocated outputs); on exit the caller's stream waits
+    for the mesh stream, so a tensor handed back (or written in place) is complete for any
+    later use or free on the caller's stream.  `inputs` that the library keeps reading after
+    the call are marked as used on the mesh stream."""
+    torch = _torch()
+    cur = torch.cuda.current_stream(mesh.device)
+    other = cur != mesh.stream
+    if other:
+        mesh.stream.wait_stream(cur)
+        for t in inputs:
+            if t is not None:
+                t.record_stream(mesh.stream)
+    yield
+    if other:
+        cur.wait_stream(mesh.stream)
+
+
 class Mesh:
     """A tetrahedral mesh with its DG operators (host set-up, then bound to a device workspace)."""
 
@@ -143,9 +166,11 @@ class Mesh:
         _check(_lib.dgrtm_mesh_bytes(self.h, C.byref(nb)), "dgrtm_mesh_bytes")
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
-        _check(_lib.dgrtm_mesh_bind(self.h, self.ws.data_ptr(), nb.value, C.c_void_p(self.stream.cuda_stream)),
-               "dgrtm_mesh_bind")
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        with _ordered(self):
+            _check(_lib.dgrtm_mesh_bind(self.h, self.ws.data_ptr(), nb.value, C.c_void_p(self.stream.cuda_stream)),
+                   "dgrtm_mesh_bind")
         return self
 
     def export_setup(self):
@@ -174,7 +199,7 @@ class Mesh:
         return {"Dr": Dr, "Ds": Ds, "Dt": Dt, "LIFT": L, "rst": rst}
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.dgrtm_mesh_destroy(self.h)
             self.h = None
 
@@ -223,10 +248,12 @@ class Shot:
         nb = C.c_size_t()
         _check(_lib.dgrtm_shot_bytes(mesh.h, C.byref(a), C.byref(nb)), "dgrtm_shot_bytes")
         self.bytes = nb.value
-        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=mesh.device)
+        with torch.cuda.stream(mesh.stream):
+            self.ws = torch.empty(nb.value, dtype=torch.uint8, device=mesh.device)
         h = C.c_void_p()
-        _check(_lib.dgrtm_shot_create(mesh.h, C.byref(a), self.ws.data_ptr(), nb.value, C.byref(h)),
-               "dgrtm_shot_create")
+        with _ordered(mesh):
+            _check(_lib.dgrtm_shot_create(mesh.h, C.byref(a), self.ws.data_ptr(), nb.value, C.byref(h)),
+                   "dgrtm_shot_create")
         self.h = h
         self.n_rec = int(a.n_rec)
 
@@ -235,53 +262,65 @@ class Shot:
         torch = _torch()
         if traces is None and self.n_rec:
             traces = torch.empty((self.n_rec, self.n_global + 1), dtype=torch.float32, device=self.mesh.device)
-        _check(_lib.dgrtm_forward(self.h, None if traces is None else traces.data_ptr()), "dgrtm_forward")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_forward(self.h, None if traces is None else traces.data_ptr()), "dgrtm_forward")
         return traces
 
     def adjoint(self, data, condition: int = IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start: int = 0):
         u = np.ascontiguousarray(up, dtype=np.float64)
-        _check(_lib.dgrtm_adjoint(self.h, None if data is None else data.data_ptr(), int(condition), _ptr(u),
-                                  int(g_image_start)), "dgrtm_adjoint")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_adjoint(self.h, None if data is None else data.data_ptr(), int(condition), _ptr(u),
+                                      int(g_image_start)), "dgrtm_adjoint")
 
     def image(self, out=None, accumulate: bool = False):
         torch = _torch()
         if out is None:
             out = torch.zeros((self.mesh.K, self.mesh.Np), dtype=torch.float64, device=self.mesh.device)
-        _check(_lib.dgrtm_image(self.h, out.data_ptr(), int(accumulate)), "dgrtm_image")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_image(self.h, out.data_ptr(), int(accumulate)), "dgrtm_image")
         return out
 
     def residual(self, a, b) -> float:
         r = C.c_double()
-        _check(_lib.dgrtm_residual(self.h, a.data_ptr(), b.data_ptr(), a.numel(), C.byref(r)), "dgrtm_residual")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_residual(self.h, a.data_ptr(), b.data_ptr(), a.numel(), C.byref(r)),
+                   "dgrtm_residual")
         return r.value
 
     # ---- test hooks
     def apply_rhs(self, q, reversed_time: bool = False):
         torch = _torch()
         out = torch.empty_like(q)
-        _check(_lib.dgrtm_apply_rhs(self.h, q.data_ptr(), out.data_ptr(), int(reversed_time)), "dgrtm_apply_rhs")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_apply_rhs(self.h, q.data_ptr(), out.data_ptr(), int(reversed_time)),
+                   "dgrtm_apply_rhs")
         return out
 
     def set_state(self, which: int, q, h1=None, h2=None):
-        _check(_lib.dgrtm_set_state(self.h, int(which), None if q is None else q.data_ptr(),
-                                    None if h1 is None else h1.data_ptr(), None if h2 is None else h2.data_ptr()),
-               "dgrtm_set_state")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_set_state(self.h, int(which), None if q is None else q.data_ptr(),
+                                        None if h1 is None else h1.data_ptr(),
+                                        None if h2 is None else h2.data_ptr()), "dgrtm_set_state")
 
     def get_state(self, which: int):
         torch = _torch()
         out = torch.empty((self.mesh.K, 4, self.mesh.Np), dtype=torch.float32, device=self.mesh.device)
-        _check(_lib.dgrtm_get_state(self.h, int(which), out.data_ptr()), "dgrtm_get_state")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_get_state(self.h, int(which), out.data_ptr()), "dgrtm_get_state")
         return out
 
     def run(self, which: int, n_global: int, reversed_time: bool = False, with_source: bool = False):
-        _check(_lib.dgrtm_run(self.h, int(which), int(n_global), int(reversed_time), int(with_source)), "dgrtm_run")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_run(self.h, int(which), int(n_global), int(reversed_time), int(with_source)),
+                   "dgrtm_run")
 
     # ---- pipeline (continuous batching)
     def begin(self, data=None, condition: int = IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start: int = 0):
         self._up = np.ascontiguousarray(up, dtype=np.float64)
         self._data = data
-        _check(_lib.dgrtm_shot_begin(self.h, None if data is None else data.data_ptr(), int(condition),
-                                     _ptr(self._up), int(g_image_start)), "dgrtm_shot_begin")
+        with _ordered(self.mesh, data):
+            _check(_lib.dgrtm_shot_begin(self.h, None if data is None else data.data_ptr(), int(condition),
+                                         _ptr(self._up), int(g_image_start)), "dgrtm_shot_begin")
 
     def state(self):
         ph, done, total = C.c_int(), C.c_int64(), C.c_int64()
@@ -292,7 +331,8 @@ class Shot:
         """The shot's own recorded traces (device copy)."""
         torch = _torch()
         out = torch.empty((self.n_rec, self.n_global + 1), dtype=torch.float32, device=self.mesh.device)
-        _check(_lib.dgrtm_shot_traces(self.h, out.data_ptr()), "dgrtm_shot_traces")
+        with _ordered(self.mesh):
+            _check(_lib.dgrtm_shot_traces(self.h, out.data_ptr()), "dgrtm_shot_traces")
         return out
 
     # ---- measurement
@@ -306,7 +346,7 @@ class Shot:
         return {"kernel_ms": ms.value, "launches": n.value, "element_steps": es.value}
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.dgrtm_shot_destroy(self.h)
             self.h = None
 
@@ -314,4 +354,7 @@ class Shot:
 def step_shots(shots, n_global: int = 1):
     """Advance several shots of one mesh by n_global global steps of their pipelines, batched."""
     arr = (C.c_void_p * len(shots))(*[s.h for s in shots])
-    _check(_lib.dgrtm_step_shots(arr, len(shots), int(n_global)), "dgrtm_step_shots")
+    if not shots:
+        return
+    with _ordered(shots[0].mesh):
+        _check(_lib.dgrtm_step_shots(arr, len(shots), int(n_global)), "dgrtm_step_shots")

@@ -26,3 +26,25 @@ def test_serving_mix_equals_alone():
     for r in (rs, rb):
         s = r.summary()
         assert s["shots"] == 6 and s["latency_p99_s"] >= s["latency_p50_s"] > 0
+
+
+def test_outputs_ordered_against_a_busy_mesh_stream():
+    """A shot's image and traces read from the caller's stream while the mesh's own stream
+    still holds queued steps of another shot must come back complete."""
+    from paper_1506_00907_amd import dgrtm, serving as S
+    pool = S.MeshSlotPool("two_layer_small:4:4:3:4", n_rec=4)
+    reqs = S.make_requests(2, 200.0, [pool.name], t_final=0.02, seed=5)
+    with torch.cuda.stream(pool.stream):
+        a = dgrtm.Shot(pool.mesh, pool.spec(reqs[0]))
+        tr = a.forward()
+        a.adjoint(tr, dgrtm.IMAGE_CHARACTERISTIC, (0.0, 0.0, 1.0), 0)
+        want_img = a.image().cpu().numpy()
+        want_tr = a.traces().cpu().numpy()
+        b = pool.new_shot(reqs[1])
+        dgrtm.step_shots([b], 2 * b.n_global)          # queued on the mesh stream only
+    got_img = a.image().cpu().numpy()                  # caller's (default) stream
+    got_tr = a.traces().cpu().numpy()
+    assert np.linalg.norm(want_img) > 0
+    assert np.array_equal(got_img, want_img)
+    assert np.array_equal(got_tr, want_tr)
+    pool.sync()
