@@ -32,7 +32,10 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     units = [
         ("setup.cpp", ["-ffp-contract=off"]),
         ("api.cpp", ["-ffp-contract=off"]),
-        ("kernels.hip", ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
+        # every atomic in the kernels is issued by one lane; the wave-level atomic rewrite would read
+        # the step kernel's tile counter back at once, behind the tile copies issued before it
+        ("kernels.hip", ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                         "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]),
     ]
     procs = []
     objs = []

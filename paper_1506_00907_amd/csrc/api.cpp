@@ -54,6 +54,7 @@ struct dgrtm_mesh_s {
   uint32_t *ops_bf16 = nullptr;
   int8_t *nbr_index = nullptr;
   int64_t *s2u = nullptr;
+  uint32_t *tile_ctr = nullptr;  // per shot slot: next-tile and finished-wave counters of the step kernel
   std::vector<int> h_eflag;  // base flags (valid, has finer neighbour)
   int64_t n_ops = 0, n_ops_bf16 = 0;
 };
@@ -160,6 +161,7 @@ static size_t mesh_layout(dgrtm_mesh m, Bump &b) {
   uint32_t *ops_bf16 = b.take<uint32_t>((size_t)n_ops_bf16);
   int8_t *nidx = b.take<int8_t>((size_t)4 * 4 * 6 * m->ref.Nfp);
   int64_t *s2u = b.take<int64_t>((size_t)K);
+  uint32_t *tctr = b.take<uint32_t>((size_t)2 * kMaxSlots);
   if (b.base) {  // a sizing pass (no base) leaves the handle untouched
     m->geo = geo;
     m->nbr = nbr;
@@ -171,6 +173,7 @@ static size_t mesh_layout(dgrtm_mesh m, Bump &b) {
     m->ops_bf16 = ops_bf16;
     m->nbr_index = nidx;
     m->s2u = s2u;
+    m->tile_ctr = tctr;
   }
   return b.used;
 }
@@ -258,6 +261,9 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
   HIPCHK(hipMemcpyAsync(m->ops_bf16, fragb.data(), fragb.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(m->nbr_index, nidx.data(), nidx.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(m->s2u, h.sorted_to_user.data(), K * 8, hipMemcpyHostToDevice, st));
+  // the step kernel leaves its counters at zero when it ends; they start at zero here
+  const std::vector<uint32_t> zero(2 * kMaxSlots, 0u);
+  HIPCHK(hipMemcpyAsync(m->tile_ctr, zero.data(), zero.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   m->bound = true;
   return DGRTM_OK;
@@ -531,6 +537,7 @@ static StepArgs mesh_args(dgrtm_mesh m, int precision, int mode, bool reversed, 
   a.ops = m->ops;
   a.ops_bf16 = m->ops_bf16;
   a.nbr_index = m->nbr_index;
+  a.tile_ctr = m->tile_ctr;
   a.Ktot = h.Ktot;
   a.L = h.L;
   fill_level_begin(h, a.lev_begin);

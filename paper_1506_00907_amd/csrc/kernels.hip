@@ -225,8 +225,9 @@ __device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np
 // QLDS: the old state comes from an LDS tile in the quad layout (field c, node n of element e at
 // lqix(c, n, e)) instead of global memory; HLDS: the two older rhs come from LDS tiles (sh1, sh2).
 // TR2 (needs both): no per-lane stores of the state, the rhs or the traces; the new state replaces
-// the old one in sq, the new rhs the first older rhs in sh1 and the half-step state the second in
-// sh2, for tile_traces and store_rows to write out with 16-byte stores.
+// the first older rhs in sh1, the new rhs the second in sh2 and the half-step state the old state in
+// sq, for tile_traces and the block stores to write out with 16-byte stores (the old state's tile
+// is then the first to be free for the next tile's copies).
 template <int N, int MODE, bool QLDS = false, bool HLDS = false, bool TR2 = false>
 __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
                                           int64_t m, int flag, float *sq, int e,
@@ -276,7 +277,25 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         }
     }
   }
-  if (!valid) return;
+  if (!valid) {
+    if constexpr (TR2) {
+      // a padding element keeps its state and passes its history on, as the per-lane path does
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int n = 16 * rt + 4 * g + i;
+          if (!(16 * rt + 15 < Np || n < Np)) continue;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float h = sh1[lqix<N>(c, n, e)];
+            sh2[lqix<N>(c, n, e)] = h;
+            sh1[lqix<N>(c, n, e)] = sq[lqix<N>(c, n, e)];
+          }
+        }
+    }
+    return;
+  }
   if constexpr (MODE == MODE_RHS_ONLY) {
 #pragma unroll
     for (int rt = 0; rt < NR; ++rt)
@@ -380,9 +399,9 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         qn[c] = qo[i][c] + dtl * (kA0 * r[c] + kA1 * h1[i][c] + kA2 * h2[i][c]);
         qm[c] = qo[i][c] + dtl * (kB0 * r[c] + kB1 * h1[i][c] + kB2 * h2[i][c]);
         if constexpr (TR2) {   // (these slots were read above and are not read again)
-          sq[lqix<N>(c, n, e)] = qn[c];
-          sh1[lqix<N>(c, n, e)] = r[c];
-          sh2[lqix<N>(c, n, e)] = qm[c];
+          sh1[lqix<N>(c, n, e)] = qn[c];
+          sh2[lqix<N>(c, n, e)] = r[c];
+          sq[lqix<N>(c, n, e)] = qm[c];
         } else {
           R0[idx] = r[c];
           q[idx] = qn[c];
@@ -532,6 +551,12 @@ __device__ __forceinline__ void lds_copy4(const void *g, uint32_t lds) {
                : "memory", "m0");
 }
 #define DGRTM_WAIT_VM(n) asm volatile("s_waitcnt vmcnt(" #n ")" ::: "memory")
+// at most n vector-memory instructions outstanding (n a compile-time count)
+template <int n>
+__device__ __forceinline__ void wait_vm_at_most() {
+  static_assert(n >= 0 && n <= 63, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(n) : "memory");
+}
 
 // one tile's block of ROWS rows x 16 floats (contiguous, 16-byte aligned) -> LDS, 1 KB per copy
 template <int ROWS>
@@ -594,9 +619,24 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
   const SlotArgs &sl = a.slot[blockIdx.y];
-  const int64_t tstride = 4 * (int64_t)gridDim.x;
+  // Tiles.  Wavefront w of work-group b takes tiles 4 b + w and then 4 b + w + W (W wavefronts in
+  // the grid).  A launch with at least 3 W tiles hands out the rest in order from the slot's
+  // counter, and its wavefronts start about a quarter of a tile apart, so that their bursts of
+  // copies and stores (and those of every other work-group, which run in step) interleave instead
+  // of all reaching the memory system at once; the wavefronts that start later take fewer tiles.
+  // A smaller launch keeps the stride W throughout and starts at once.
+  const int64_t nfirst = 4 * (int64_t)gridDim.x;
+  const bool dyn = ntiles >= 3 * nfirst;
+  uint32_t *const ctr = a.tile_ctr + 2 * blockIdx.y;
+  auto grab = [&]() -> uint32_t {   // the returned value is read only after an explicit wait
+    uint32_t v = 0u;
+    if (lane == 0) v = atomicAdd(ctr, 1u);
+    return v;
+  };
   int64_t tile = (int64_t)blockIdx.x * 4 + wave;
-  if (tile >= ntiles) return;
+  if (tile >= ntiles) return;   // (never when dyn, where tile < W <= ntiles)
+  if (dyn)
+    for (int i = 0; i < wave; ++i) __builtin_amdgcn_s_sleep(127);
   float *const q_t = stile[wave];
   float *const g_t = q_t + QW;
   float *const n_t = g_t + DD::GW;
@@ -616,13 +656,15 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       cd[f] = a.ncode[tix(4, f, kk)];
     }
   };
-  auto issue_tile = [&](int64_t t) {
+  // a tile's state
+  auto issue_q = [&](int64_t t) { copy_block<16 * NK>(sl.q + t * QW, lq, lane); };
+  // a tile's geometry and its neighbours' face runs (nb, cd: the tile's neighbour ids and codes)
+  auto issue_gt = [&](int64_t t, const int (&nbs)[4], const int (&cds)[4]) {
     const int64_t k0 = t * 16;
-    copy_block<16 * NK>(sl.q + (k0 >> 4) * QW, lq, lane);
     copy_block<kGeo>(a.geo + tix(kGeo, 0, k0), lg, lane);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const int nb = nbv[f], code = codev[f];
+      const int nb = nbs[f], code = cds[f];
       const int f2 = code & 3, perm = (code >> 2) & 7, shn = a.L - (code >> 5);
       const int slot = nb >= 0 ? (((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2) : 0;
       const float *trp = sl.tr + (int64_t)slot * Dm::TRS * K;
@@ -650,19 +692,37 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
 #pragma unroll
   for (int f = 0; f < 4; ++f) asm volatile("" : "+v"(nbv[f]), "+v"(codev[f]));
   asm volatile("" : "+v"(flag));
-  issue_tile(tile);
+  issue_q(tile);
+  issue_gt(tile, nbv, codev);
+  DGRTM_WAIT_VM(0);
+  int64_t nxt = tile + nfirst;
+
+  // Order of a tile's vector-memory traffic (vmcnt counts loads and stores in issue order):
+  //   top      wait until at most SW are outstanding: the previous tile's SW block stores may still
+  //            run, everything issued before them (this tile's copies) has landed; issue the history
+  //   surface  (forward and recompute) the next tile's geometry and neighbour runs, into tiles that
+  //            this tile no longer reads
+  //   end      traces of the new state; the next tile's state (and, for the image step, geometry
+  //            and neighbour runs); then the SW block stores of the new state and the new rhs
+  constexpr bool EARLY_GT = HIST && MODE != MODE_IMAGE;
+  constexpr int SW = HIST ? 2 * NK : 0;   // 16 NK rows per block store: NK instructions each
 
   while (true) {
-    // the fields, geometry and neighbour traces of this tile have landed
+    // this tile's state, geometry and neighbour runs have landed, and every LDS read of the
+    // previous tile is done
     __builtin_amdgcn_sched_barrier(0);
-    DGRTM_WAIT_VM(0);
+    wait_vm_at_most<SW>();
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (HIST) issue_hist(tile);
     __builtin_amdgcn_sched_barrier(0);
     const int64_t k = tile * 16 + e;
-    const int64_t nxt = tile + tstride;
     int nbn[4], coden[4], flagn = 0;
-    if (nxt < ntiles) load_elem(nxt, nbn, coden, flagn);   // lands while this tile computes
+    uint32_t vnn = 0u;
+    if (nxt < ntiles) {   // both land while this tile computes
+      if (dyn) vnn = grab();
+      load_elem(nxt, nbn, coden, flagn);
+    }
     const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
     const int sh = a.L - lev;
     const int64_t m = sl.tau >> sh;
@@ -785,28 +845,62 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int f = 0; f < 4; ++f) asm volatile("" : "+v"(nbn[f]), "+v"(coden[f]));
-    asm volatile("" : "+v"(flagn));
+    asm volatile("" : "+v"(flagn), "+v"(vnn));
+    // the tile after the next
+    const int64_t nn = dyn ? 2 * nfirst + __builtin_amdgcn_readfirstlane(vnn) : nxt + nfirst;
+    const bool more = nxt < ntiles;
+    if constexpr (EARLY_GT) {
+      // the geometry tile was read at the top and the neighbour runs by the surface terms
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      if (more) issue_gt(nxt, nbn, coden);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     tile_tail<N, MODE, true, HIST, HIST>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy,
                                        rvz, h_t, h_t + QW, sseg);
     if constexpr (HIST) {
-      tile_traces<N>(a, sl, k, g, e, m, flag, q_t, h_t + QW, nfx, nfy, nfz);
+      tile_traces<N>(a, sl, k, g, e, m, flag, h_t, q_t, nfx, nfy, nfz);
+      // the old-state tile (half-step state by now) and, for the image step, the segment rows in
+      // the geometry and neighbour tiles have been read
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) {
+        issue_q(nxt);
+        if constexpr (!EARLY_GT) issue_gt(nxt, nbn, coden);
+      }
+      __builtin_amdgcn_sched_barrier(0);
       // new state and new rhs of the tile: element-contiguous rows, 16 bytes per lane
       const int64_t k0 = tile * 16;
-      store_block<16 * NK>(q_t, sl.q + (k0 >> 4) * QW, lane);
-      store_block<16 * NK>(h_t, sl.ring + (m % 3) * ((int64_t)state_row(Np) * K) + (k0 >> 4) * QW, lane);
+      store_block<16 * NK>(h_t, sl.q + (k0 >> 4) * QW, lane);
+      store_block<16 * NK>(h_t + QW, sl.ring + (m % 3) * ((int64_t)state_row(Np) * K) + (k0 >> 4) * QW, lane);
+    } else {
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) {
+        issue_q(nxt);
+        issue_gt(nxt, nbn, coden);
+      }
     }
-    if (nxt >= ntiles) break;
-    // every LDS access of this tile has completed before the next tile's copies may land
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
+    if (!more) break;
     tile = nxt;
+    nxt = nn;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       nbv[f] = nbn[f];
       codev[f] = coden[f];
     }
     flag = flagn;
-    issue_tile(tile);
+  }
+  if (dyn) {
+    // the last work-group to finish clears the counters for the next launch (every wavefront of a
+    // dyn launch reaches this point)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t done = atomicAdd(ctr + 1, 1u);
+      if (done + 1u == gridDim.x) {
+        ctr[0] = 0u;
+        ctr[1] = 0u;
+      }
+    }
   }
 }
 

@@ -83,6 +83,10 @@ struct StepArgs {
   const float *ops;                   // FP32 operator fragments (build_op_fragments)
   const uint32_t *ops_bf16;           // split-BF16 operator fragments (build_op_fragments_bf16)
   const int8_t *nbr_index;            // [4][4][6][Nfp]
+  // [kMaxSlots][2] per shot slot: tiles handed out beyond the first two per wavefront, and
+  // work-groups finished; zero between launches (the last work-group to finish clears them), so
+  // launches that share them must not overlap (one stream per mesh)
+  uint32_t *tile_ctr;
   int64_t Ktot;
   int L;                              // number of levels
   int64_t lev_begin[kMaxLevels + 1];  // index l-1 -> first position of level l (finest first)
