@@ -234,7 +234,8 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
                                           v4f (&rp)[Dims<N>::NR], v4f (&rvx)[Dims<N>::NR], v4f (&rvy)[Dims<N>::NR],
                                           v4f (&rvz)[Dims<N>::NR], float *sh1 = nullptr,
-                                          float *sh2 = nullptr, const float *sseg = nullptr) {
+                                          float *sh2 = nullptr, const float *sseg = nullptr,
+                                          const double *imv_pre = nullptr) {
   constexpr Tab<N> T{};
   constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F, NR = Dims<N>::NR;
   const int64_t K = a.Ktot;
@@ -383,7 +384,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
             srv[i][1] = srp[(jS + 1) * Np * Pl + tix(Np, nn, kk)];
             srv[i][2] = srp[jS * Np * Pl + tix(Np, nn, kk)];
           }
-          imv[i] = sl.img[tix(Np, nn, k)];
+          imv[i] = imv_pre ? imv_pre[rt * 4 + i] : sl.img[tix(Np, nn, k)];
         }
       }
     }
@@ -821,6 +822,7 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
         }
     }
     const float *sseg = nullptr;
+    double imv[NR * 4];   // the image at this lane's nodes (image step), loaded with the segment rows
     if constexpr (MODE == MODE_IMAGE) {
       // the source-wavefield segment rows this receiver step correlates with go to the geometry
       // and neighbour-trace tiles, which the tile no longer reads
@@ -838,6 +840,13 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
         copy_block<Np>(sl.seg_r + orr + (jS + 1) * Np * Pl + tix(Np, 0, kk0), lg + 8 * Np * 16, lane);
         copy_block<Np>(sl.seg_r + orr + jS * Np * Pl + tix(Np, 0, kk0), lg + 12 * Np * 16, lane);
         sseg = g_t;
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int n = 16 * rt + 4 * g + i;
+            imv[rt * 4 + i] = sl.img[tix(Np, (16 * rt + 15 < Np || n < Np) ? n : 0, k)];   // (rows past Np unused)
+          }
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -856,7 +865,7 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       __builtin_amdgcn_sched_barrier(0);
     }
     tile_tail<N, MODE, true, HIST, HIST>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy,
-                                       rvz, h_t, h_t + QW, sseg);
+                                       rvz, h_t, h_t + QW, sseg, MODE == MODE_IMAGE ? imv : nullptr);
     if constexpr (HIST) {
       tile_traces<N>(a, sl, k, g, e, m, flag, h_t, q_t, nfx, nfy, nfz);
       // the old-state tile (half-step state by now) and, for the image step, the segment rows in
