@@ -576,6 +576,18 @@ __device__ __forceinline__ void store_block(const float *lds, float *dst, int la
       *reinterpret_cast<float4 *>(dst + 256 * j + 4 * lane) = *reinterpret_cast<const float4 *>(lds + 256 * j + 4 * lane);
 }
 
+// NBYTES (a multiple of 16) from global to LDS by LDS copies, 1 KB per wavefront instruction, the
+// work-group's four wavefronts taking alternate kilobytes
+template <int NBYTES>
+__device__ __forceinline__ void stage_dma(const void *src, void *dst, int wave, int lane) {
+  static_assert(NBYTES % 16 == 0, "16-byte copies");
+  constexpr int NCH = (NBYTES + 1023) / 1024;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+    if ((c & 3) == wave && c * 1024 + 16 * lane < NBYTES)
+      lds_copy16(reinterpret_cast<const char *>(src) + c * 1024 + 16 * lane, lds_addr(dst) + c * 1024);
+}
+
 template <int N>
 struct DmaDims {
   static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, FC = Dims<N>::FC;
@@ -602,20 +614,6 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   __shared__ __align__(16) float stile[4][DD::WAVE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = lane & 15, g = lane >> 4;
-  // volume operator fragments -> registers (A operands of every volume product of every tile)
-  float fD[3][NR][NK];
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int rt = 0; rt < NR; ++rt)
-#pragma unroll
-      for (int c = 0; c < NK; ++c) fD[j][rt][c] = a.ops[((j * NR + rt) * NK + c) * 64 + lane];
-  stage_to_lds<NR * 4 * FC * 64>(a.ops + 3 * NR * NK * 64, sL);
-  stage_to_lds<Dm::TABW>(a.nbr_index, stabw);
-  // all of the above has landed (a builtin wait, so that the compiler places no wait for the
-  // operator registers inside the tile loop, where it would also wait for the tile copies)
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
   const int8_t *stab = reinterpret_cast<const int8_t *>(stabw);
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
@@ -635,9 +633,7 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     return v;
   };
   int64_t tile = (int64_t)blockIdx.x * 4 + wave;
-  if (tile >= ntiles) return;   // (never when dyn, where tile < W <= ntiles)
-  if (dyn)
-    for (int i = 0; i < wave; ++i) __builtin_amdgcn_s_sleep(127);
+  const bool live = tile < ntiles;   // (always when dyn, where tile < W <= ntiles)
   float *const q_t = stile[wave];
   float *const g_t = q_t + QW;
   float *const n_t = g_t + DD::GW;
@@ -659,10 +655,10 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   };
   // a tile's state
   auto issue_q = [&](int64_t t) { copy_block<16 * NK>(sl.q + t * QW, lq, lane); };
-  // a tile's geometry and its neighbours' face runs (nb, cd: the tile's neighbour ids and codes)
-  auto issue_gt = [&](int64_t t, const int (&nbs)[4], const int (&cds)[4]) {
-    const int64_t k0 = t * 16;
-    copy_block<kGeo>(a.geo + tix(kGeo, 0, k0), lg, lane);
+  // a tile's geometry
+  auto issue_g = [&](int64_t t) { copy_block<kGeo>(a.geo + tix(kGeo, 0, t * 16), lg, lane); };
+  // a tile's neighbours' face runs (nb, cd: the tile's neighbour ids and codes)
+  auto issue_t = [&](int64_t t, const int (&nbs)[4], const int (&cds)[4]) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       const int nb = nbs[f], code = cds[f];
@@ -679,6 +675,10 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       (void)perm;
     }
   };
+  auto issue_gt = [&](int64_t t, const int (&nbs)[4], const int (&cds)[4]) {
+    issue_g(t);
+    issue_t(t, nbs, cds);
+  };
   // the two older rhs of a tile: issued once the tile's fields have landed, so that they travel
   // while the tile's operator products run instead of in the same burst as the fields
   auto issue_hist = [&](int64_t t) {
@@ -689,12 +689,33 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     copy_block<16 * NK>(sl.ring + ((m + 2) % 3) * slab + (k0 >> 4) * QW, lh, lane);
     copy_block<16 * NK>(sl.ring + ((m + 1) % 3) * slab + (k0 >> 4) * QW, lh + 4 * QW, lane);
   };
-  load_elem(tile, nbv, codev, flag);
+  // the first tile's state, geometry and element data travel while the operators are staged
+  if (live) {
+    issue_q(tile);
+    issue_g(tile);
+    load_elem(tile, nbv, codev, flag);
+  }
+  // volume operator fragments -> registers (A operands of every volume product of every tile)
+  float fD[3][NR][NK];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+      for (int c = 0; c < NK; ++c) fD[j][rt][c] = a.ops[((j * NR + rt) * NK + c) * 64 + lane];
+  stage_dma<4 * NR * 4 * FC * 64>(a.ops + 3 * NR * NK * 64, sL, wave, lane);
+  stage_dma<4 * Dm::TABW>(a.nbr_index, stabw, wave, lane);
+  // all of the above has landed (a builtin wait, so that the compiler places no wait for the
+  // operator registers inside the tile loop, where it would also wait for the tile copies)
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (!live) return;
 #pragma unroll
   for (int f = 0; f < 4; ++f) asm volatile("" : "+v"(nbv[f]), "+v"(codev[f]));
   asm volatile("" : "+v"(flag));
-  issue_q(tile);
-  issue_gt(tile, nbv, codev);
+  issue_t(tile, nbv, codev);
+  if (dyn)
+    for (int i = 0; i < wave; ++i) __builtin_amdgcn_s_sleep(127);
   DGRTM_WAIT_VM(0);
   int64_t nxt = tile + nfirst;
 
