@@ -143,6 +143,39 @@ SHOT_SHAPES = {
 }
 
 
+def precision_compare(dgrtm, I, mesh, box, src_xy, n_rec, t_final, esteps_global, dof):
+    """One shot of the same workload (shorter simulated time) in both forms: throughput of each and
+    the split-BF16 result's relative L2 difference from the FP32 result on the same shot."""
+    import numpy as np
+    import torch
+    spec = I.rtm_shot(box=box, src_xy=src_xy, n_rec=n_rec, t_final=t_final)
+    res = {}
+    for prec in (dgrtm.FP32, dgrtm.SPLIT_BF16):
+        sh = dgrtm.Shot(mesh, dgrtm.ShotSpec(t_final=spec.t_final, src=spec.src, f_peak=spec.f_peak,
+                                             t_peak=spec.t_peak, rec=spec.rec, precision=prec))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        tr = sh.forward()
+        sh.adjoint(tr, condition=dgrtm.IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start=0)
+        im = sh.image()
+        torch.cuda.synchronize()
+        res[prec] = (time.perf_counter() - ts, tr.cpu().numpy(), im.cpu().numpy(), sh.n_global)
+        log(f"{'split-BF16' if prec else 'FP32'} comparison shot: {res[prec][0]:.2f} s")
+        del sh
+    ng = res[dgrtm.FP32][3]
+    gdof = 3 * ng * esteps_global * dof / 1e9
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(float(np.linalg.norm(b)), 1e-300))
+
+    f, b = res[dgrtm.FP32], res[dgrtm.SPLIT_BF16]
+    return {"value": round(gdof / b[0], 3), "unit": "GDOF-steps/s",
+            "dtype": "split-bf16 operator products (hi*hi + hi*lo + lo*hi), fp32 accumulation and state",
+            "t_final_s": t_final, "global_steps": int(ng), "ms_per_shot": round(1e3 * b[0], 1),
+            "fp32_same_shot": {"value": round(gdof / f[0], 3), "ms_per_shot": round(1e3 * f[0], 1)},
+            "rel_l2_vs_fp32_same_shot": {"traces": rel(b[1], f[1]), "image": rel(b[2], f[2])}}
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -210,6 +243,8 @@ def main():
     ap.add_argument("--t-final", type=float, default=1.0)
     ap.add_argument("--sample-every", type=int, default=7, help="time every n-th step-kernel launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bf16-t-final", type=float, default=0.25,
+                    help="simulated time of the split-BF16 vs FP32 comparison shot (0 = skip)")
     ap.add_argument("--serving", type=int, default=0, help="requests in the serving section (0 = skip)")
     ap.add_argument("--serving-t-final", type=float, default=0.05)
     ap.add_argument("--traffic-from-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -317,6 +352,10 @@ def main():
                      "frac": round(rl[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
                      "traffic": tr, "per_mode": rl},
     }
+    if args.bf16_t_final > 0:
+        log(f"split-BF16 vs FP32 comparison shots (t_f = {args.bf16_t_final} s) ...")
+        out["split_bf16"] = precision_compare(dgrtm, I, mesh, mm.box, src_xy, shape["n_rec"], args.bf16_t_final,
+                                              esteps_global, dof)
     if args.serving > 0:
         del shot, traces, img
         log(f"serving: {args.serving} requests ...")

@@ -228,7 +228,9 @@ __device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np
 // the first older rhs in sh1, the new rhs the second in sh2 and the half-step state the old state in
 // sq, for tile_traces and the block stores to write out with 16-byte stores (the old state's tile
 // is then the first to be free for the next tile's copies).
-template <int N, int MODE, bool QLDS = false, bool HLDS = false, bool TR2 = false>
+// PRE (image step): the tile's segment rows are in LDS at sseg and the image values at the lane's
+// nodes in imv_pre, both loaded before the update.
+template <int N, int MODE, bool QLDS = false, bool HLDS = false, bool TR2 = false, bool PRE = false>
 __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
                                           int64_t m, int flag, float *sq, int e,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
@@ -371,7 +373,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         for (int i = 0; i < 4; ++i) {
           const int n = 16 * rt + 4 * g + i;
           const int nn = (16 * rt + 15 < Np || n < Np) ? n : 0;   // (rows past Np are not used)
-          if (sseg) {   // the tile's segment rows, already in LDS: [q][r(jS+2)][r(jS+1)][r(jS)] x Np x 16
+          if constexpr (PRE) {   // the tile's segment rows, in LDS: [q][r(jS+2)][r(jS+1)][r(jS)] x Np x 16
             sqv[i] = sseg[(0 * Np + nn) * 16 + e];
             srv[i][0] = sseg[(1 * Np + nn) * 16 + e];
             srv[i][1] = sseg[(2 * Np + nn) * 16 + e];
@@ -384,7 +386,8 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
             srv[i][1] = srp[(jS + 1) * Np * Pl + tix(Np, nn, kk)];
             srv[i][2] = srp[jS * Np * Pl + tix(Np, nn, kk)];
           }
-          imv[i] = imv_pre ? imv_pre[rt * 4 + i] : sl.img[tix(Np, nn, k)];
+          if constexpr (PRE) imv[i] = imv_pre[rt * 4 + i];
+          else imv[i] = sl.img[tix(Np, nn, k)];
         }
       }
     }
@@ -588,6 +591,29 @@ __device__ __forceinline__ void stage_dma(const void *src, void *dst, int wave, 
       lds_copy16(reinterpret_cast<const char *>(src) + c * 1024 + 16 * lane, lds_addr(dst) + c * 1024);
 }
 
+// C += A_hi B_hi + A_hi B_lo + A_lo B_hi (A: uint4 fragment with hi in x, y and lo in z, w)
+#define DGRTM_MF3(A, BH, BL, C)                                                                          \
+  do {                                                                                                   \
+    const v4s ah_ = __builtin_bit_cast(v4s, uint2{(A).x, (A).y});                                        \
+    const v4s al_ = __builtin_bit_cast(v4s, uint2{(A).z, (A).w});                                        \
+    C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah_, BH, C, 0, 0, 0);                                  \
+    C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah_, BL, C, 0, 0, 0);                                  \
+    C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al_, BH, C, 0, 0, 0);                                  \
+  } while (0)
+
+// Split-BF16 form: every operator product A x is evaluated as A_hi x_hi + A_hi x_lo + A_lo x_hi
+// on v_mfma_f32_16x16x16_bf16 with FP32 accumulation (A = A_hi + A_lo and x = x_hi + x_lo in
+// bf16).  Lane l holds A[l%16][4(l/16)..4(l/16)+3] and B[4(l/16)..+3][l%16]; C as above.
+// Operator fragments: per (operator, row tile, 16-column chunk) 64 lanes x (4 hi + 4 lo) bf16.
+template <int N>
+struct DimsB {
+  static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, NR = Dims<N>::NR;
+  static constexpr int NK = (Np + 15) / 16;    // 16-column chunks of D_j
+  static constexpr int FC = (Nfp + 15) / 16;   // 16-column chunks per face of LIFT
+  static constexpr int FRAG = 3 * NR * NK + NR * 4 * FC;          // fragments
+  static constexpr int OPS_U4 = FRAG * 64;                        // uint4 per fragment lane
+};
+
 template <int N>
 struct DmaDims {
   static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, FC = Dims<N>::FC;
@@ -601,16 +627,19 @@ struct DmaDims {
   static constexpr int WAVE = QW + GW + TW + 2 * QW;  // LDS words per wavefront
 };
 
-template <int N, int MODE>
+template <int N, int MODE, int PREC>
 __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   constexpr Tab<N> T{};
   using Dm = Dims<N>;
   using DD = DmaDims<N>;
+  using DB = DimsB<N>;
   constexpr int Np = Dm::Np, Nfp = Dm::Nfp, F = Dm::F, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
   constexpr int QW = DD::QW;
   constexpr bool HIST = MODE != MODE_RHS_ONLY;
+  // LIFT fragments: FP32 [NR][4 FC][64] floats, or split-BF16 [NR][4 FC_B][64] x (4 hi + 4 lo) bf16
+  constexpr int SLW = PREC ? NR * 4 * DB::FC * 64 * 4 : NR * 4 * FC * 64;
   __shared__ __align__(16) uint32_t stabw[Dm::TABW];
-  __shared__ __align__(16) float sL[NR * 4 * FC * 64];
+  __shared__ __align__(16) float sL[SLW];
   __shared__ __align__(16) float stile[4][DD::WAVE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = lane & 15, g = lane >> 4;
@@ -696,14 +725,26 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     load_elem(tile, nbv, codev, flag);
   }
   // volume operator fragments -> registers (A operands of every volume product of every tile)
-  float fD[3][NR][NK];
+  float fD[3][NR][NK];          // FP32
+  uint4 fDb[3][NR][DB::NK];     // split-BF16: hi in (x, y), lo in (z, w)
+  if constexpr (PREC == 0) {
 #pragma unroll
-  for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int rt = 0; rt < NR; ++rt)
+      for (int rt = 0; rt < NR; ++rt)
 #pragma unroll
-      for (int c = 0; c < NK; ++c) fD[j][rt][c] = a.ops[((j * NR + rt) * NK + c) * 64 + lane];
-  stage_dma<4 * NR * 4 * FC * 64>(a.ops + 3 * NR * NK * 64, sL, wave, lane);
+        for (int c = 0; c < NK; ++c) fD[j][rt][c] = a.ops[((j * NR + rt) * NK + c) * 64 + lane];
+    stage_dma<4 * SLW>(a.ops + 3 * NR * NK * 64, sL, wave, lane);
+  } else {
+    const uint4 *ob = reinterpret_cast<const uint4 *>(a.ops_bf16);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+        for (int c = 0; c < DB::NK; ++c) fDb[j][rt][c] = ob[((j * NR + rt) * DB::NK + c) * 64 + lane];
+    stage_dma<4 * SLW>(ob + 3 * NR * DB::NK * 64, sL, wave, lane);
+  }
   stage_dma<4 * Dm::TABW>(a.nbr_index, stabw, wave, lane);
   // all of the above has landed (a builtin wait, so that the compiler places no wait for the
   // operator registers inside the tile loop, where it would also wait for the tile copies)
@@ -760,26 +801,63 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     v4f cp[NR], w0[NR], w1[NR], w2[NR];
 #pragma unroll
     for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+    if constexpr (PREC == 0) {
 #pragma unroll
-    for (int c = 0; c < NK; ++c) {
-      const int mm = 4 * c + g;
-      const bool ok = 4 * c + 3 < Np || mm < Np;
-      const int mr = ok ? mm : 0;
-      const float p = ok ? q_t[lqix<N>(0, mr, e)] : 0.f;
-      const float vx = ok ? q_t[lqix<N>(1, mr, e)] : 0.f;
-      const float vy = ok ? q_t[lqix<N>(2, mr, e)] : 0.f;
-      const float vz = ok ? q_t[lqix<N>(3, mr, e)] : 0.f;
-      const float Ur = rx * vx + ry * vy + rz * vz;
-      const float Us = sx * vx + sy * vy + sz * vz;
-      const float Ut = tx * vx + ty * vy + tz * vz;
+      for (int c = 0; c < NK; ++c) {
+        const int mm = 4 * c + g;
+        const bool ok = 4 * c + 3 < Np || mm < Np;
+        const int mr = ok ? mm : 0;
+        const float p = ok ? q_t[lqix<N>(0, mr, e)] : 0.f;
+        const float vx = ok ? q_t[lqix<N>(1, mr, e)] : 0.f;
+        const float vy = ok ? q_t[lqix<N>(2, mr, e)] : 0.f;
+        const float vz = ok ? q_t[lqix<N>(3, mr, e)] : 0.f;
+        const float Ur = rx * vx + ry * vy + rz * vz;
+        const float Us = sx * vx + sy * vy + sz * vz;
+        const float Ut = tx * vx + ty * vy + tz * vz;
 #pragma unroll
-      for (int rt = 0; rt < NR; ++rt) {
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[0][rt][c], Ur, cp[rt], 0, 0, 0);
-        w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[0][rt][c], p, w0[rt], 0, 0, 0);
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[1][rt][c], Us, cp[rt], 0, 0, 0);
-        w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[1][rt][c], p, w1[rt], 0, 0, 0);
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[2][rt][c], Ut, cp[rt], 0, 0, 0);
-        w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[2][rt][c], p, w2[rt], 0, 0, 0);
+        for (int rt = 0; rt < NR; ++rt) {
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[0][rt][c], Ur, cp[rt], 0, 0, 0);
+          w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[0][rt][c], p, w0[rt], 0, 0, 0);
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[1][rt][c], Us, cp[rt], 0, 0, 0);
+          w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[1][rt][c], p, w1[rt], 0, 0, 0);
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[2][rt][c], Ut, cp[rt], 0, 0, 0);
+          w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fD[2][rt][c], p, w2[rt], 0, 0, 0);
+        }
+      }
+    } else {
+      // lane (e, g) supplies B rows 16 c + 4 g .. + 3: node quad 4 c + g of each field, one
+      // 16-byte LDS read each (quads past the last hold no nodes and give zeros)
+#pragma unroll
+      for (int c = 0; c < DB::NK; ++c) {
+        const int qd = 4 * c + g;
+        const bool ok = 4 * c + 3 < NK || qd < NK;
+        const int qr = ok ? qd : 0;
+        float4 p4 = *reinterpret_cast<const float4 *>(&q_t[lqix<N>(0, 4 * qr, e)]);
+        float4 x4 = *reinterpret_cast<const float4 *>(&q_t[lqix<N>(1, 4 * qr, e)]);
+        float4 y4 = *reinterpret_cast<const float4 *>(&q_t[lqix<N>(2, 4 * qr, e)]);
+        float4 z4 = *reinterpret_cast<const float4 *>(&q_t[lqix<N>(3, 4 * qr, e)]);
+        if (!ok) p4 = x4 = y4 = z4 = float4{0.f, 0.f, 0.f, 0.f};
+        const float pv[4] = {p4.x, p4.y, p4.z, p4.w}, xv[4] = {x4.x, x4.y, x4.z, x4.w};
+        const float yv[4] = {y4.x, y4.y, y4.z, y4.w}, zv[4] = {z4.x, z4.y, z4.z, z4.w};
+        v4s urh, url, ush, usl, uth, utl, ph, pl;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          short h, l;
+          split_bf16(rx * xv[v] + ry * yv[v] + rz * zv[v], h, l); urh[v] = h; url[v] = l;
+          split_bf16(sx * xv[v] + sy * yv[v] + sz * zv[v], h, l); ush[v] = h; usl[v] = l;
+          split_bf16(tx * xv[v] + ty * yv[v] + tz * zv[v], h, l); uth[v] = h; utl[v] = l;
+          split_bf16(pv[v], h, l); ph[v] = h; pl[v] = l;
+        }
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt) {
+          const uint4 ar = fDb[0][rt][c], as = fDb[1][rt][c], at = fDb[2][rt][c];
+          DGRTM_MF3(ar, urh, url, cp[rt]);
+          DGRTM_MF3(as, ush, usl, cp[rt]);
+          DGRTM_MF3(at, uth, utl, cp[rt]);
+          DGRTM_MF3(ar, ph, pl, w0[rt]);
+          DGRTM_MF3(as, ph, pl, w1[rt]);
+          DGRTM_MF3(at, ph, pl, w2[rt]);
+        }
       }
     }
     v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
@@ -809,28 +887,59 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       v4f G[NR];
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int cc = 0; cc < FC; ++cc) {
-        const bool sv = 4 * cc + 3 < Nfp || 4 * cc + g < Nfp;   // face node 4 cc + g exists
-        const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
-                              T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
+      // the penalty terms at face node s (volume node `node`; zero unless sv: s exists)
+      auto pen = [&](int s, int node, bool sv, float &mPp, float &Pv) {
         const float pm = q_t[lqix<N>(0, node, e)];
         const float nvm = nx * q_t[lqix<N>(1, node, e)] + ny * q_t[lqix<N>(2, node, e)] + nz * q_t[lqix<N>(3, node, e)];
-        // the neighbour's node matching face node 4 cc + g of this face
-        const int t = stab[((f * 4 + f2) * 6 + perm) * Nfp + min(4 * cc + g, Nfp - 1)];
+        // the neighbour's node matching face node s of this face
+        const int t = stab[((f * 4 + f2) * 6 + perm) * Nfp + min(s, Nfp - 1)];
         const int toff = (t >> 2) * 64 + e * 4 + (t & 3);
         const float tp = inner ? n_t[(2 * f + 0) * 16 * Dm::FS + toff] : 0.0f;
         const float tv = inner ? n_t[(2 * f + 1) * 16 * Dm::FS + toff] : 0.0f;
         const float pp = cP * pm + tp;
         const float nvp = -(cP * nvm + tv);
         const float dp = pp - pm, dnv = nvp - nvm;
-        const float mPp = sv ? -0.5f * rc2 * (dnv - taup * dp) * Fs : 0.0f;
-        const float Pv = sv ? 0.5f * irho * (dp - tauv * dnv) * Fs : 0.0f;
+        mPp = sv ? -0.5f * rc2 * (dnv - taup * dp) * Fs : 0.0f;
+        Pv = sv ? 0.5f * irho * (dp - tauv * dnv) * Fs : 0.0f;
+      };
+      if constexpr (PREC == 0) {
 #pragma unroll
-        for (int rt = 0; rt < NR; ++rt) {
-          const float al = sL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
-          rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
-          G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
+        for (int cc = 0; cc < FC; ++cc) {   // lane (e, g) takes face node 4 cc + g
+          const bool sv = 4 * cc + 3 < Nfp || 4 * cc + g < Nfp;
+          const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
+                                T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
+          float mPp, Pv;
+          pen(4 * cc + g, node, sv, mPp, Pv);
+#pragma unroll
+          for (int rt = 0; rt < NR; ++rt) {
+            const float al = sL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
+            rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
+            G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
+          }
+        }
+      } else {
+        const uint4 *sLb = reinterpret_cast<const uint4 *>(sL);
+#pragma unroll
+        for (int cc = 0; cc < DB::FC; ++cc) {   // lane (e, g) takes face nodes 16 cc + 4 g + v
+          v4s pph, ppl, pvh, pvl;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int s = 16 * cc + 4 * g + v;
+            const bool sv = 16 * cc + 12 + v < Nfp || s < Nfp;
+            const int node = sel4(g, T.fmask[f][min(16 * cc + v, Nfp - 1)], T.fmask[f][min(16 * cc + 4 + v, Nfp - 1)],
+                                  T.fmask[f][min(16 * cc + 8 + v, Nfp - 1)], T.fmask[f][min(16 * cc + 12 + v, Nfp - 1)]);
+            float mPp, Pv;
+            pen(s, node, sv, mPp, Pv);
+            short h, l;
+            split_bf16(mPp, h, l); pph[v] = h; ppl[v] = l;
+            split_bf16(Pv, h, l); pvh[v] = h; pvl[v] = l;
+          }
+#pragma unroll
+          for (int rt = 0; rt < NR; ++rt) {
+            const uint4 al = sLb[(rt * 4 * DB::FC + f * DB::FC + cc) * 64 + lane];
+            DGRTM_MF3(al, pph, ppl, rp[rt]);
+            DGRTM_MF3(al, pvh, pvl, G[rt]);
+          }
         }
       }
 #pragma unroll
@@ -885,8 +994,9 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       if (more) issue_gt(nxt, nbn, coden);
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE, true, HIST, HIST>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy,
-                                       rvz, h_t, h_t + QW, sseg, MODE == MODE_IMAGE ? imv : nullptr);
+    tile_tail<N, MODE, true, HIST, HIST, MODE == MODE_IMAGE>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy,
+                                                          nfz, rp, rvx, rvy, rvz, h_t, h_t + QW, sseg,
+                                                          MODE == MODE_IMAGE ? imv : nullptr);
     if constexpr (HIST) {
       tile_traces<N>(a, sl, k, g, e, m, flag, h_t, q_t, nfx, nfy, nfz);
       // the old-state tile (half-step state by now) and, for the image step, the segment rows in
@@ -1048,19 +1158,6 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, nullptr, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
   }
 }
-
-// Split-BF16 form: every operator product A x is evaluated as A_hi x_hi + A_hi x_lo + A_lo x_hi
-// on v_mfma_f32_16x16x16_bf16 with FP32 accumulation (A = A_hi + A_lo and x = x_hi + x_lo in
-// bf16).  Lane l holds A[l%16][4(l/16)..4(l/16)+3] and B[4(l/16)..+3][l%16]; C as above.
-// Operator fragments: per (operator, row tile, 16-column chunk) 64 lanes x (4 hi + 4 lo) bf16.
-template <int N>
-struct DimsB {
-  static constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, NR = Dims<N>::NR;
-  static constexpr int NK = (Np + 15) / 16;    // 16-column chunks of D_j
-  static constexpr int FC = (Nfp + 15) / 16;   // 16-column chunks per face of LIFT
-  static constexpr int FRAG = 3 * NR * NK + NR * 4 * FC;          // fragments
-  static constexpr int OPS_U4 = FRAG * 64;                        // uint4 per fragment lane
-};
 
 template <int N, int MODE, bool OPS_LDS>
 __global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
@@ -1342,22 +1439,22 @@ static int64_t device_cus() {
 template <int N, int MODE>
 static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
   const int64_t groups = (a.k_end / 16 + 3) / 4;
-  // a persistent-style grid: each work-group stages the operators once and then takes tile groups
-  const int64_t cap = a.max_groups > 0 ? a.max_groups : 2 * device_cus();
-  const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, cap)), (unsigned)a.nslots), block(256);
-  if (a.precision == 1) {
-    constexpr size_t lds = (size_t)DimsB<N>::OPS_U4 * sizeof(uint4);
-    if constexpr (lds <= 96 * 1024) {
-      static bool done = false;
-      hipError_t e = ensure_lds(step_kernel_bf16<N, MODE, true>, lds, done);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((step_kernel_bf16<N, MODE, true>), grid, block, lds, st, a);
-    } else {
-      hipLaunchKernelGGL((step_kernel_bf16<N, MODE, false>), grid, block, 0, st, a);
-    }
-    return hipGetLastError();
-  }
   if constexpr (N >= 5) {
+    // a persistent-style grid: each work-group stages the operators once and then takes tile groups
+    const int64_t cap = a.max_groups > 0 ? a.max_groups : 2 * device_cus();
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, cap)), (unsigned)a.nslots), block(256);
+    if (a.precision == 1) {
+      constexpr size_t lds = (size_t)DimsB<N>::OPS_U4 * sizeof(uint4);
+      if constexpr (lds <= 96 * 1024) {
+        static bool done = false;
+        hipError_t e = ensure_lds(step_kernel_bf16<N, MODE, true>, lds, done);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((step_kernel_bf16<N, MODE, true>), grid, block, lds, st, a);
+      } else {
+        hipLaunchKernelGGL((step_kernel_bf16<N, MODE, false>), grid, block, 0, st, a);
+      }
+      return hipGetLastError();
+    }
     constexpr size_t lds_lr = Dims<N>::OPS * sizeof(float);
     if constexpr (lds_lr <= 96 * 1024) {
       static bool done = false;
@@ -1368,10 +1465,13 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
       hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, false>), grid, block, 0, st, a);
     }
   } else {
-    // one work-group per CU (its static LDS fills the CU); each loops over tile groups
-    const dim3 gridp((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
-                     (unsigned)a.nslots);
-    hipLaunchKernelGGL((step_kernel_dma<N, MODE>), gridp, block, 0, st, a);
+    // one work-group per CU (its static LDS fills the CU); each loops over tiles
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
+                    (unsigned)a.nslots), block(256);
+    if (a.precision == 1)
+      hipLaunchKernelGGL((step_kernel_dma<N, MODE, 1>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((step_kernel_dma<N, MODE, 0>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }

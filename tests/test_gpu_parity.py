@@ -175,9 +175,9 @@ def test_split_bf16_forward_100_steps(name, nl):
     assert rel(tr, tr_ref) < 1e-4
 
 
-def test_split_bf16_image():
+@pytest.mark.parametrize("name", ["two_layer_small:6:6:4:2", "two_layer_small:4:4:3:4"])
+def test_split_bf16_image(name):
     from paper_1506_00907_amd import dgrtm
-    name = "two_layer_small:6:6:4:2"
     lm, mm, rho, c, N = lib_mesh(name, BC_TRANSPARENT, 3)
     m, op, lev, L, dtl = case(name, bc=BC_TRANSPARENT, n_levels=3)
     spec = I.rtm_shot(n_rec=4)
