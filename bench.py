@@ -342,7 +342,8 @@ def main():
         "config": {"workload": args.workload, "elements": int(mesh.K), "order_N": int(N), "levels": int(L),
                    "level_histogram_coarse_to_fine": [int(x) for x in hist], "global_steps": int(ng),
                    "t_final_s": round(ng * mesh.dt_local * 2 ** (L - 1), 6), "receivers": int(shot.n_rec),
-                   "image": "characteristic", "parallelism": "single GPU"},
+                   "image": "characteristic", "parallelism": "single GPU",
+                   "shot_workspace_GB": round(shot.bytes / 1e9, 2)},
         "images_per_hour": round(3600.0 * args.steps / wall, 2),
         "shot_latency_s": {"p50": round(float(np.percentile(lat, 50)), 3),
                            "p99": round(float(np.percentile(lat, 99)), 3)},
@@ -352,12 +353,14 @@ def main():
                      "frac": round(rl[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
                      "traffic": tr, "per_mode": rl},
     }
+    # the timed shot's workspace (checkpoints and segment records) is released before the other
+    # sections allocate theirs: on the largest meshes one shot's workspace is most of the HBM
+    del shot, traces, img
     if args.bf16_t_final > 0:
         log(f"split-BF16 vs FP32 comparison shots (t_f = {args.bf16_t_final} s) ...")
         out["split_bf16"] = precision_compare(dgrtm, I, mesh, mm.box, src_xy, shape["n_rec"], args.bf16_t_final,
                                               esteps_global, dof)
     if args.serving > 0:
-        del shot, traces, img
         log(f"serving: {args.serving} requests ...")
         out["serving"] = serving_bench(args.serving, args.serving_t_final)
     if not args.no_cpu_baseline:

@@ -48,22 +48,24 @@ class Mesh:
         return int(self.etov.shape[0])
 
 
-def graded_layers(z0: float, z1: float, n: int, fine: list[tuple[float, float]]) -> np.ndarray:
-    """n+1 layer positions on [z0, z1]; cells inside the `fine` intervals get half thickness.
+def graded_layers(z0: float, z1: float, n: int, fine: list[tuple]) -> np.ndarray:
+    """n+1 layer positions on [z0, z1]; cells inside a `fine` interval (a, b) get half thickness,
+    inside (a, b, w) 1/w of the thickness.
 
-    The positions are the inverse of the cumulative of a weight that is 2 in the
+    The positions are the inverse of the cumulative of a weight that is w (default 2) in the
     fine intervals and 1 elsewhere, sampled at n equal steps.
     """
+    fine = [tuple(f) if len(f) == 3 else (f[0], f[1], 2.0) for f in fine]
     # breakpoints of the piecewise-constant weight
     pts = {z0, z1}
-    for a, b in fine:
+    for a, b, _ in fine:
         pts.add(min(max(a, z0), z1))
         pts.add(min(max(b, z0), z1))
     pts = np.array(sorted(pts))
     mids = 0.5 * (pts[:-1] + pts[1:])
     w = np.ones_like(mids)
-    for a, b in fine:
-        w[(mids > a) & (mids < b)] = 2.0
+    for a, b, wf in fine:
+        w[(mids > a) & (mids < b)] = float(wf)
     cum = np.concatenate([[0.0], np.cumsum(w * np.diff(pts))])
     target = np.linspace(0.0, cum[-1], n + 1)
     idx = np.clip(np.searchsorted(cum, target, side="right") - 1, 0, len(w) - 1)
@@ -226,12 +228,14 @@ def two_layer_model(mesh: Mesh, c_top=1.5, c_bottom=3.0, rho=1.0):
     return np.full(mesh.K, float(rho)), c
 
 
-def graded_top_mesh(nx, ny, nz, box=(10.0, 10.0, 4.0), top=0.5, jitter=0.1, seed=5) -> Mesh:
-    """Box whose top `top` km has half-thickness cells (the largest single-GPU shot)."""
+def graded_top_mesh(nx, ny, nz, box=(10.0, 10.0, 4.0), top=0.5, refine=4.0, jitter=0.1, seed=5) -> Mesh:
+    """Box whose top `top` km has cells 1/refine as thick as below (the largest single-GPU shot:
+    with refine = 4 and velocities over a 3x range the element time steps span more than 8x,
+    hence four LTS levels)."""
     Lx, Ly, Lz = box
     xs = np.linspace(0.0, Lx, nx + 1)
     ys = np.linspace(0.0, Ly, ny + 1)
-    zl = graded_layers(0.0, Lz, nz, [(Lz - top, Lz)])
+    zl = graded_layers(0.0, Lz, nz, [(Lz - top, Lz, refine)])
     verts, etov = kuhn_box(xs, ys, lambda i: zl)
     zc = np.tile(zl, (nx + 1, 1))
     nv = verts.shape[0]
