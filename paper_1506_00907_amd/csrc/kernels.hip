@@ -1045,29 +1045,50 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
 }
 
 // The FP32 step kernel for N >= 5, with the tile mapping and MFMA layout of step_kernel_dma.  Its
-// operators do not leave room in registers or LDS for the pipelined tiles, so it loads the
-// fields chunk by chunk straight from HBM, with the operator fragments in LDS when they fit.
+// operators (in LDS when they fit, else read through the caches) leave room in LDS for one tile
+// per wavefront, but not for the neighbour runs and the history: each wavefront's state and
+// geometry tiles come by LDS copies, issued for the next tile as soon as the update has read the
+// state; neighbour traces and the older rhs are read per lane.
 template <int N, int MODE, bool OPS_LDS>
 __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   constexpr Tab<N> T{};
   using Dm = Dims<N>;
+  using DD = DmaDims<N>;
   constexpr int Np = Dm::Np, Nfp = Dm::Nfp, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
-  extern __shared__ float sops[];
-  const float *ops = a.ops;
-  if constexpr (OPS_LDS) {
-    stage_to_lds<Dm::OPS>(a.ops, sops);
-    __syncthreads();
-    ops = sops;
-  }
+  constexpr int QW = DD::QW, GW = DD::GW;
+  // N = 6 has no registers to spare: one volume chunk at a time, neighbour traces read per chunk
+  constexpr bool LEAN = N >= 6;
+  constexpr int VU = LEAN ? 1 : 2;
+  extern __shared__ __align__(16) float sdyn[];   // [operators if OPS_LDS][4 wavefronts][QW + GW]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = lane & 15, g = lane >> 4;
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
   const SlotArgs &sl = a.slot[blockIdx.y];
+  float *const q_t = sdyn + (OPS_LDS ? Dm::OPS : 0) + wave * (QW + GW);
+  float *const g_t = q_t + QW;
+  const uint32_t lq = __builtin_amdgcn_readfirstlane(lds_addr(q_t));
+  const uint32_t lg = lq + 4 * QW;
+  const int64_t tstride = 4 * (int64_t)gridDim.x;
+  int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  auto issue = [&](int64_t t) {
+    copy_block<16 * NK>(sl.q + t * QW, lq, lane);
+    copy_block<kGeo>(a.geo + tix(kGeo, 0, t * 16), lg, lane);
+  };
+  if (tile < ntiles) issue(tile);
+  const float *ops = a.ops;
+  if constexpr (OPS_LDS) {
+    stage_dma<4 * Dm::OPS>(a.ops, sdyn, wave, lane);
+    ops = sdyn;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
-  for (int64_t grp = blockIdx.x; grp * 4 < ntiles; grp += gridDim.x) {
-    const int64_t tile = grp * 4 + wave;
-    if (tile >= ntiles) continue;
+  for (; tile < ntiles; tile += tstride) {
+    // this tile's state and geometry have landed
+    __builtin_amdgcn_sched_barrier(0);
+    DGRTM_WAIT_VM(0);
+    __builtin_amdgcn_sched_barrier(0);
     const int64_t k = tile * 16 + e;
     // an opaque zero keeps the operator-fragment reads inside the tile loop (hoisting them out
     // would pin every fragment in registers for the whole kernel)
@@ -1082,7 +1103,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
 
     float gg[kGeo];
 #pragma unroll
-    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[tix(kGeo, i, k)];
+    for (int i = 0; i < kGeo; ++i) gg[i] = g_t[i * 16 + e];
     const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
                 tz = gg[8];
     const float rc2 = gg[9], irho = gg[10];
@@ -1091,16 +1112,15 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     v4f cp[NR], w0[NR], w1[NR], w2[NR];
 #pragma unroll
     for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
+#pragma unroll VU
     for (int c = 0; c < NK; ++c) {
       const int mm = 4 * c + g;
-      float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
-      if (mm < Np) {
-        p = sl.q[qix(node_quads(Np), 0, mm, k)];
-        vx = sl.q[qix(node_quads(Np), 1, mm, k)];
-        vy = sl.q[qix(node_quads(Np), 2, mm, k)];
-        vz = sl.q[qix(node_quads(Np), 3, mm, k)];
-      }
+      const bool ok = mm < Np;
+      const int mr = ok ? mm : 0;
+      const float p = ok ? q_t[lqix<N>(0, mr, e)] : 0.f;
+      const float vx = ok ? q_t[lqix<N>(1, mr, e)] : 0.f;
+      const float vy = ok ? q_t[lqix<N>(2, mr, e)] : 0.f;
+      const float vz = ok ? q_t[lqix<N>(3, mr, e)] : 0.f;
       const float Ur = rx * vx + ry * vy + rz * vz;
       const float Us = sx * vx + sy * vy + sz * vz;
       const float Ut = tx * vx + ty * vy + tz * vz;
@@ -1126,18 +1146,38 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     for (int f = 0; f < 4; ++f) {
       const FaceCtx fc = face_ctx<N>(a, sl, f, k, gg);
       nfx[f] = fc.nx; nfy[f] = fc.ny; nfz[f] = fc.nz;
+      // boundary states without branches (cP = 1 rigid wall, -1 free surface, 0 otherwise)
+      const bool inner = fc.nb >= 0;
+      const float cP = fc.nb == -1 ? 1.0f : (fc.nb == -3 ? -1.0f : 0.0f);
+      // the neighbour's traces at this lane's face nodes (all chunks at once unless LEAN)
+      auto nbtrace = [&](int cc, float &p_, float &v_) {
+        const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::FS +
+                           fc.tab[inner ? min(4 * cc + g, Nfp - 1) : 0];
+        p_ = inner ? nbt[0] : 0.0f;
+        v_ = inner ? nbt[Dm::TRC] : 0.0f;
+      };
+      float tp[FC], tv[FC];
+      if constexpr (!LEAN) {
+#pragma unroll
+        for (int cc = 0; cc < FC; ++cc) nbtrace(cc, tp[cc], tv[cc]);
+      }
       v4f G[NR];
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int cc = 0; cc < FC; ++cc) {
-        const int s = 4 * cc + g;   // face node handled by this lane in this chunk
-        float mPp = 0.f, Pv = 0.f;
-        if (4 * cc + 3 < Nfp || s < Nfp) {
-          const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
-                                T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
-          penalty<N>(a, sl.q, fc, s, node, k, rc2, irho, mPp, Pv);
-        }
+        const bool sv = 4 * cc + 3 < Nfp || 4 * cc + g < Nfp;   // face node 4 cc + g exists
+        const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
+                              T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
+        const float pm = q_t[lqix<N>(0, node, e)];
+        const float nvm = fc.nx * q_t[lqix<N>(1, node, e)] + fc.ny * q_t[lqix<N>(2, node, e)] +
+                          fc.nz * q_t[lqix<N>(3, node, e)];
+        if constexpr (LEAN) nbtrace(cc, tp[cc], tv[cc]);
+        const float pp = cP * pm + tp[cc];
+        const float nvp = -(cP * nvm + tv[cc]);
+        const float dp = pp - pm, dnv = nvp - nvm;
+        const float mPp = sv ? -0.5f * rc2 * (dnv - fc.taup * dp) * fc.Fs : 0.0f;
+        const float Pv = sv ? 0.5f * irho * (dp - fc.tauv * dnv) * fc.Fs : 0.0f;
 #pragma unroll
         for (int rt = 0; rt < NR; ++rt) {
           const float al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
@@ -1155,7 +1195,11 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, nullptr, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    tile_tail<N, MODE, true>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    // every LDS read of this tile is done: the next tile's copies may land
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    if (tile + tstride < ntiles) issue(tile + tstride);
   }
 }
 
@@ -1455,14 +1499,21 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
       }
       return hipGetLastError();
     }
-    constexpr size_t lds_lr = Dims<N>::OPS * sizeof(float);
-    if constexpr (lds_lr <= 96 * 1024) {
+    // one work-group per CU: the operators (when they fit) and one state tile per wavefront
+    constexpr size_t tiles = (size_t)4 * (DmaDims<N>::QW + DmaDims<N>::GW) * sizeof(float);
+    constexpr size_t lds_ops = (size_t)Dims<N>::OPS * sizeof(float);
+    const dim3 grid1((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
+                     (unsigned)a.nslots);
+    if constexpr (lds_ops + tiles <= 160 * 1024) {
       static bool done = false;
-      hipError_t e = ensure_lds(step_kernel_lowreg<N, MODE, true>, lds_lr, done);
+      hipError_t e = ensure_lds(step_kernel_lowreg<N, MODE, true>, lds_ops + tiles, done);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, true>), grid, block, lds_lr, st, a);
+      hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, true>), grid1, block, lds_ops + tiles, st, a);
     } else {
-      hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, false>), grid, block, 0, st, a);
+      static bool done = false;
+      hipError_t e = ensure_lds(step_kernel_lowreg<N, MODE, false>, tiles, done);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, false>), grid1, block, tiles, st, a);
     }
   } else {
     // one work-group per CU (its static LDS fills the CU); each loops over tiles
