@@ -210,7 +210,10 @@ def traffic_from_pmc(workload: str, fetch_dir: str, write_dir: str, copy_fetch_d
             n = r["Kernel_Name"]
             if "step_kernel" not in n:
                 continue
-            mode = int(n.split("<")[1].split(",")[1].split(">")[0])
+            targs = [t.strip() for t in n.split("<")[1].split(">")[0].split(",")]
+            if "step_kernel_dma" in n and len(targs) > 2 and targs[2] != "0":
+                continue   # the split-BF16 form's launches (same bytes; the roofline line is FP32)
+            mode = int(targs[1])
             per.setdefault(names.get(mode, str(mode)), {"fetch": [], "write": []})[key].append(
                 float(r["Counter_Value"]) * 1024.0 * scale)
     modes = {m: {"fetch_bytes_per_launch": sum(v["fetch"]) / len(v["fetch"]),

@@ -1516,9 +1516,12 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
       hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, false>), grid1, block, tiles, st, a);
     }
   } else {
-    // one work-group per CU (its static LDS fills the CU); each loops over tiles
-    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
-                    (unsigned)a.nslots), block(256);
+    // one work-group per CU (its static LDS fills the CU); each loops over tiles.  A launch with
+    // fewer than two tiles per wavefront of a full grid takes a smaller grid with two tiles per
+    // wavefront (the second tile's copies overlap the first tile's work)
+    const int64_t cus = a.max_groups > 0 ? a.max_groups : device_cus();
+    const int64_t g2 = (a.k_end / 16 < 8 * cus) ? (a.k_end / 16 + 7) / 8 : groups;
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(g2, cus)), (unsigned)a.nslots), block(256);
     if (a.precision == 1)
       hipLaunchKernelGGL((step_kernel_dma<N, MODE, 1>), grid, block, 0, st, a);
     else
