@@ -223,6 +223,14 @@ dgrtm_status dgrtm_residual(dgrtm_shot shot, const float *a, const float *b, int
 
 /* ---- test hooks (device arrays in user order: n_elem x 4 fields (p, vx, vy, vz) x Np) ---- */
 
+/* Cap on the work-groups of the mesh's step launches (max_groups > 0), or the default grid
+ * (max_groups = 0: about one work-group per compute unit).  A cap well above the number of compute
+ * units gives every wavefront fixed tiles at a fixed stride, which turns off the counter hand-out
+ * and the staggered starts of large launches: results are the same bit for bit, which is what
+ * the tests check.
+ * Host only; applies to later launches.  Errors: DGRTM_ERR_ARG (null mesh, negative cap). */
+dgrtm_status dgrtm_mesh_set_launch_cap(dgrtm_mesh mesh, int64_t max_groups);
+
 /* Right-hand side of the semi-discrete system for the given state (no source), forward time
  * (reversed = 0) or reversed time -L(q; -tau) (reversed = 1).  Uses the shot's source-field buffers. */
 dgrtm_status dgrtm_apply_rhs(dgrtm_shot shot, const float *q, float *rhs, int reversed);

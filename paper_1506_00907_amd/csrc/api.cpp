@@ -55,6 +55,7 @@ struct dgrtm_mesh_s {
   int8_t *nbr_index = nullptr;
   int64_t *s2u = nullptr;
   uint32_t *tile_ctr = nullptr;  // per shot slot: next-tile and finished-wave counters of the step kernel
+  int64_t max_groups = 0;        // cap on step-launch work-groups (0: one per compute unit)
   std::vector<int> h_eflag;  // base flags (valid, has finer neighbour)
   int64_t n_ops = 0, n_ops_bf16 = 0;
 };
@@ -266,6 +267,12 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
   HIPCHK(hipMemcpyAsync(m->tile_ctr, zero.data(), zero.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   m->bound = true;
+  return DGRTM_OK;
+}
+
+extern "C" dgrtm_status dgrtm_mesh_set_launch_cap(dgrtm_mesh m, int64_t max_groups) {
+  if (!m || max_groups < 0) return fail(DGRTM_ERR_ARG, "dgrtm_mesh_set_launch_cap: bad argument");
+  m->max_groups = max_groups;
   return DGRTM_OK;
 }
 
@@ -538,6 +545,7 @@ static StepArgs mesh_args(dgrtm_mesh m, int precision, int mode, bool reversed, 
   a.ops_bf16 = m->ops_bf16;
   a.nbr_index = m->nbr_index;
   a.tile_ctr = m->tile_ctr;
+  a.max_groups = m->max_groups;
   a.Ktot = h.Ktot;
   a.L = h.L;
   fill_level_begin(h, a.lev_begin);

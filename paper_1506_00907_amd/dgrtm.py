@@ -30,6 +30,7 @@ _SYMBOLS = {
                                     C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "dgrtm_mesh_bytes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "dgrtm_mesh_bind": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dgrtm_mesh_set_launch_cap": (C.c_int32, [C.c_void_p, C.c_int64]),
     "dgrtm_export_setup": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dgrtm_export_operators": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
     "dgrtm_mesh_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
@@ -171,6 +172,11 @@ class Mesh:
         with _ordered(self):
             _check(_lib.dgrtm_mesh_bind(self.h, self.ws.data_ptr(), nb.value, C.c_void_p(self.stream.cuda_stream)),
                    "dgrtm_mesh_bind")
+        return self
+
+    def set_launch_cap(self, max_groups: int):
+        """Test hook: cap the work-groups of the step launches (0 = default grid)."""
+        _check(_lib.dgrtm_mesh_set_launch_cap(self.h, int(max_groups)), "dgrtm_mesh_set_launch_cap")
         return self
 
     def export_setup(self):

@@ -1,0 +1,107 @@
+"""Full-size checks on the 201 600-element two-layer mesh (N = 4) in the launch configuration the
+benchmark times.  Launches with at least three tiles per wavefront hand tiles out from a per-slot
+counter and stagger the starts of their wavefronts; no small mesh triggers that, so these tests
+run the benchmark's mesh:
+
+- the right-hand side against the FP64 oracle on sampled elements (the oracle evaluates them one
+  by one from the same state);
+- a whole shot (forward, checkpointed recompute, backward with image) with the counter hand-out
+  against the same shot with every wavefront on fixed tiles: bit for bit;
+- two shots sharing every launch (two slots, two counters) against each shot alone: bit for bit.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAME = "rtm_200k"
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.fixture(scope="module")
+def big():
+    from paper_1506_00907_amd import dgrtm, inputs as I
+    mm, rho, c, N = I.config_mesh(NAME)
+    lm = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, 3).bind("cuda")
+    assert lm.K == 201600 and lm.L == 3
+    return lm, mm, rho, c, N
+
+
+def _spec(mm, src_xy, n_global, lm, ckpt_interval):
+    from paper_1506_00907_amd import dgrtm, inputs as I
+    s = I.rtm_shot(box=mm.box, src_xy=src_xy, n_rec=20, t_final=1.0)
+    t_final = n_global * lm.dt_local * 2 ** (lm.L - 1)
+    # an early pulse, so that the short run carries a real wavefield
+    return dgrtm.ShotSpec(t_final=t_final, src=s.src, f_peak=s.f_peak, t_peak=0.002, rec=s.rec,
+                          ckpt_interval=ckpt_interval)
+
+
+def _alone(lm, spec):
+    from paper_1506_00907_amd import dgrtm
+    sh = dgrtm.Shot(lm, spec)
+    tr = sh.forward()
+    q = sh.get_state(dgrtm.SOURCE_FIELD).cpu().numpy()
+    sh.adjoint(tr, dgrtm.IMAGE_CHARACTERISTIC, (0.0, 0.0, 1.0), 0)
+    img = sh.image().cpu().numpy()
+    return tr.cpu().numpy(), q, img
+
+
+@pytest.mark.parametrize("reversed_time", [False, True])
+def test_full_size_rhs_sampled_vs_oracle(big, reversed_time):
+    from oracle.dg import Operator
+    from oracle.mesh import BC_TRANSPARENT, OMesh
+    from oracle.refelem import get_ref
+    from paper_1506_00907_amd import dgrtm
+    lm, mm, rho, c, N = big
+    om = OMesh(get_ref(N), mm.verts, mm.etov, bc_default=BC_TRANSPARENT)
+    op = Operator(om, rho, c)
+    rng = np.random.default_rng(21)
+    x = om.x
+    smooth = np.sin(3.0 * x[..., 0]) * np.cos(2.0 * x[..., 1] + x[..., 2])
+    q = np.stack([smooth, 0.5 * smooth, -smooth, 0.25 * smooth], axis=1)
+    q += 0.01 * rng.standard_normal(q.shape)
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=lm.dt_local))
+    got = shot.apply_rhs(torch.from_numpy(q.astype(np.float32)).cuda(), reversed_time=reversed_time)
+    got = got.cpu().numpy()
+    el = np.sort(rng.choice(lm.K, 4000, replace=False))
+    ref = op.rhs_reversed(q, elems=el) if reversed_time else op.rhs(q, elems=el)
+    assert rel(got[el], ref) < 2e-6
+
+
+def test_full_size_counter_handout_matches_fixed_tiles(big):
+    lm, mm, rho, c, N = big
+    spec = _spec(mm, (0.7797, 1.0), 27, lm, ckpt_interval=8)   # 4 segments in the adjoint
+    lm.set_launch_cap(0)
+    a = _alone(lm, spec)
+    try:
+        lm.set_launch_cap(1 << 30)    # one work-group per tile group: fixed tiles, no stagger
+        b = _alone(lm, spec)
+    finally:
+        lm.set_launch_cap(0)
+    assert np.abs(a[0]).max() > 0 and np.abs(a[2]).max() > 0
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_full_size_two_slots_match_alone(big):
+    from paper_1506_00907_amd import dgrtm
+    lm, mm, rho, c, N = big
+    specs = [_spec(mm, (0.7797, 1.0), 19, lm, 6), _spec(mm, (1.3, 0.6), 19, lm, 6)]
+    alone = [_alone(lm, s) for s in specs]
+    shots = [dgrtm.Shot(lm, s) for s in specs]
+    for sh in shots:
+        sh.begin(None, dgrtm.IMAGE_CHARACTERISTIC, (0.0, 0.0, 1.0), 0)
+    for _ in range(10000):
+        if all(sh.state()[0] == dgrtm.PHASE_DONE for sh in shots):
+            break
+        dgrtm.step_shots(shots, 1)
+    for sh, (tr, _, img) in zip(shots, alone):
+        assert sh.state()[0] == dgrtm.PHASE_DONE
+        assert np.array_equal(sh.traces().cpu().numpy(), tr)
+        assert np.array_equal(sh.image().cpu().numpy(), img)
