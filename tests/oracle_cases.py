@@ -31,3 +31,15 @@ def eigenmode(M, t):
     q[:, 2] = pi / w * np.cos(pi * x) * np.sin(pi * y) * np.cos(pi * z) * np.sin(w * t)
     q[:, 3] = pi / w * np.cos(pi * x) * np.cos(pi * y) * np.sin(pi * z) * np.sin(w * t)
     return q
+
+
+def oracle_shot(op, lev, L, dtl, n_global, spec):
+    """The oracle's RTM shot for a shot spec (source point, Ricker wavelet, receivers)."""
+    from oracle import source as OS
+    from oracle.rtm import Shot as OShot
+    M = op.m
+    se = OS.locate(M, spec.src[None])[0]
+    sw = OS.delta_weights(M, np.array([se]), spec.src[None])[0]
+    re = OS.locate(M, spec.rec)
+    return OShot(op, lev, L, dtl, n_global, se, sw, lambda t: OS.ricker(t, spec.f_peak, spec.t_peak), re,
+                 OS.interp_rows(M, re, spec.rec), OS.delta_weights(M, re, spec.rec))

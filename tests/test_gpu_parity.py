@@ -11,7 +11,7 @@ from oracle.mesh import BC_FREE, BC_RIGID, BC_TRANSPARENT, OMesh, local_dt, lts_
 from oracle.rtm import COND_CHARACTERISTIC, COND_PRESSURE, Shot as OShot
 from oracle.refelem import get_ref
 from paper_1506_00907_amd import inputs as I
-from tests.oracle_cases import case, eigenmode
+from tests.oracle_cases import case, eigenmode, oracle_shot
 
 pytestmark = pytest.mark.gpu
 
@@ -77,12 +77,7 @@ def test_single_rate_ab3_eigenmode_100_steps():
 
 
 def _oracle_shot(name, lev, L, dtl, op, n_global, spec):
-    M = op.m
-    se = OS.locate(M, spec.src[None])[0]
-    sw = OS.delta_weights(M, np.array([se]), spec.src[None])[0]
-    re = OS.locate(M, spec.rec)
-    return OShot(op, lev, L, dtl, n_global, se, sw, lambda t: OS.ricker(t, spec.f_peak, spec.t_peak), re,
-                 OS.interp_rows(M, re, spec.rec), OS.delta_weights(M, re, spec.rec))
+    return oracle_shot(op, lev, L, dtl, n_global, spec)
 
 
 @pytest.mark.parametrize("name,nl", [("two_layer_small:6:6:4:3", 3), ("two_layer_small:5:5:3:4", 3)])

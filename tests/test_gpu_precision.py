@@ -3,15 +3,16 @@
 The 3072-tetrahedron unit cube at N = 6 (1.03 M unknowns) with the rigid-box eigenmode:
 single-rate AB3 from the exact history, relative L2 of all four fields against the oracle's
 FP64 AB3 every 100 steps up to 500 (and against the closed form).  A 3-level two-layer mesh
-at N = 6 checks the multi-rate path the same way over 100 local steps.  The measured errors
-are printed (pytest -s) and bounded: FP32 <= 1e-5 and split-BF16 <= 1e-4 after 100 steps."""
+at N = 6 checks the multi-rate path the same way over 100 local steps, and a checkpointed RTM
+shot on it the characteristic image.  The measured errors are printed (pytest -s) and bounded:
+fields FP32 <= 1e-5 and split-BF16 <= 1e-4 after 100 steps, images <= 1e-4 in both forms."""
 import numpy as np
 import pytest
 
 from oracle import timestep as T
 from oracle.mesh import BC_RIGID, BC_TRANSPARENT
 from paper_1506_00907_amd import inputs as I
-from tests.oracle_cases import case, eigenmode
+from tests.oracle_cases import case, eigenmode, oracle_shot
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -82,3 +83,27 @@ def test_multirate_n6_100_steps(precision, tol):
     print(f"N=6 two-layer 3-level MRAB {'FP32' if precision == 0 else 'split-BF16'}: "
           f"{ng * 2 ** (L - 1)} local steps: rel L2 vs FP64 oracle {err:.3e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_image_n6(precision):
+    from paper_1506_00907_amd import dgrtm
+    name = "two_layer_small:4:4:3:6"
+    mm, rho, c, N = I.config_mesh(name)
+    lm = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, 3).bind("cuda")
+    m, op, lev, L, dtl = case(name, bc=BC_TRANSPARENT, n_levels=3)
+    spec = I.rtm_shot(n_rec=4)
+    spec.t_peak = 0.02
+    ng = 16
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=ng * dtl * 2 ** (L - 1), src=spec.src, f_peak=spec.f_peak,
+                                         t_peak=spec.t_peak, rec=spec.rec, ckpt_interval=5, precision=precision))
+    tr = shot.forward()
+    shot.adjoint(tr, dgrtm.IMAGE_CHARACTERISTIC, (0.0, 0.0, 1.0), 0)
+    img = shot.image().cpu().numpy()
+    osh = oracle_shot(op, lev, L, dtl, ng, spec)
+    osh.forward()
+    img_ref = osh.adjoint(tr.cpu().numpy().astype(np.float64))
+    err = _rel(img, img_ref)
+    print(f"N=6 characteristic image, {ng} global steps, {'FP32' if precision == 0 else 'split-BF16'}: "
+          f"rel L2 vs FP64 oracle {err:.3e}")
+    assert err <= 1e-4
