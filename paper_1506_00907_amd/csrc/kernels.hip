@@ -145,9 +145,12 @@ struct FaceCtx {
   const int8_t *tab;
 };
 
+// face f of element k: normal, J_f/J, penalty parameters, and where the neighbour's traces are
+// (nb, code: the face's neighbour entry and code)
 template <int N>
-__device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, const SlotArgs &sl, int f, int64_t k, const float *gg) {
-  constexpr int Nfp = Dims<N>::Nfp, F = Dims<N>::F;
+__device__ __forceinline__ FaceCtx face_ctx_of(const StepArgs &a, const SlotArgs &sl, int f, const float *gg, int nb,
+                                               int code) {
+  constexpr int Nfp = Dims<N>::Nfp;
   const int64_t K = a.Ktot;
   FaceCtx c;
   float nx, ny, nz;
@@ -158,8 +161,7 @@ __device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, const SlotArgs &s
   c.Fs = sqrtf(nx * nx + ny * ny + nz * nz);  // J_f / J
   const float inv = 1.0f / c.Fs;
   c.nx = nx * inv; c.ny = ny * inv; c.nz = nz * inv;
-  c.nb = a.nbr[tix(4, f, k)];
-  const int code = a.ncode[tix(4, f, k)];
+  c.nb = nb;
   c.taup = a.tau_sign * gg[12 + f];
   c.tauv = a.tau_sign * gg[16 + f];
   c.trp = sl.tr;
@@ -175,6 +177,11 @@ __device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, const SlotArgs &s
     c.tab = a.nbr_index + ((f * 4 + c.f2) * 6 + perm) * Nfp;
   }
   return c;
+}
+
+template <int N>
+__device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, const SlotArgs &sl, int f, int64_t k, const float *gg) {
+  return face_ctx_of<N>(a, sl, f, gg, a.nbr[tix(4, f, k)], a.ncode[tix(4, f, k)]);
 }
 
 // Penalty terms at face node s (volume node `node`) of the lane's element, already scaled by
@@ -230,7 +237,12 @@ __device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np
 // is then the first to be free for the next tile's copies).
 // PRE (image step): the tile's segment rows are in LDS at sseg and the image values at the lane's
 // nodes in imv_pre, both loaded before the update.
-template <int N, int MODE, bool QLDS = false, bool HLDS = false, bool TR2 = false, bool PRE = false>
+// TRQ (needs QLDS, not TR2): the new state also replaces the old one in sq, for tile_traces to write
+// the own-step traces from; only the half-step traces are written here, per lane.
+// Without HLDS / TR2 the older rhs are read, and the new rhs and state written, as one 16-byte
+// access per field and node quad.
+template <int N, int MODE, bool QLDS = false, bool HLDS = false, bool TR2 = false, bool PRE = false,
+          bool TRQ = false>
 __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
                                           int64_t m, int flag, float *sq, int e,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
@@ -349,6 +361,19 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
     float h1[4][4], h2[4][4], qo[4][4];
     float sqv[4] = {0.f, 0.f, 0.f, 0.f}, srv[4][3] = {};
     double imv[4] = {0.0, 0.0, 0.0, 0.0};
+    // node quad of this lane's four rows in this row tile (rows past the last quad hold no nodes)
+    const int qd = 4 * rt + g;
+    const bool qok = 4 * rt + 3 < NQ4 || qd < NQ4;
+    if constexpr (!HLDS) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t iq = qix(NQ4, c, 4 * (qok ? qd : 0), k);
+        const float4 a1 = *reinterpret_cast<const float4 *>(R1 + iq);
+        const float4 a2 = *reinterpret_cast<const float4 *>(R2 + iq);
+        h1[0][c] = qok ? a1.x : 0.f; h1[1][c] = qok ? a1.y : 0.f; h1[2][c] = qok ? a1.z : 0.f; h1[3][c] = qok ? a1.w : 0.f;
+        h2[0][c] = qok ? a2.x : 0.f; h2[1][c] = qok ? a2.y : 0.f; h2[2][c] = qok ? a2.z : 0.f; h2[3][c] = qok ? a2.w : 0.f;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int n = 16 * rt + 4 * g + i;
@@ -359,9 +384,6 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         if constexpr (HLDS) {
           h1[i][c] = sh1[lqix<N>(c, ok ? n : 0, e)];
           h2[i][c] = sh2[lqix<N>(c, ok ? n : 0, e)];
-        } else {
-          h1[i][c] = ok ? R1[idx] : 0.f;
-          h2[i][c] = ok ? R2[idx] : 0.f;
         }
         if constexpr (QLDS) qo[i][c] = sq[lqix<N>(c, ok ? n : 0, e)];
         else qo[i][c] = ok ? q[idx] : 0.f;
@@ -391,6 +413,26 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         }
       }
     }
+    if constexpr (!TR2) {
+      // new rhs and state of the lane's node quad, one 16-byte store per field (rows past Np in
+      // an existing quad are padding: zero operator rows and zero history leave them zero)
+      if (qok) {
+        const v4f rr[4] = {rp[rt], rvx[rt], rvy[rt], rvz[rt]};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t iq = qix(NQ4, c, 4 * qd, k);
+          float qq[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) qq[i] = qo[i][c] + dtl * (kA0 * rr[c][i] + kA1 * h1[i][c] + kA2 * h2[i][c]);
+          *reinterpret_cast<float4 *>(R0 + iq) = float4{rr[c][0], rr[c][1], rr[c][2], rr[c][3]};
+          *reinterpret_cast<float4 *>(q + iq) = float4{qq[0], qq[1], qq[2], qq[3]};
+          if constexpr (TRQ) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sq[lqix<N>(c, 4 * qd + i, e)] = qq[i];   // (read above, not again)
+          }
+        }
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int n = 16 * rt + 4 * g + i;
@@ -399,16 +441,12 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       float qn[4], qm[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int64_t idx = qix(NQ4, c, n, k);
         qn[c] = qo[i][c] + dtl * (kA0 * r[c] + kA1 * h1[i][c] + kA2 * h2[i][c]);
         qm[c] = qo[i][c] + dtl * (kB0 * r[c] + kB1 * h1[i][c] + kB2 * h2[i][c]);
         if constexpr (TR2) {   // (these slots were read above and are not read again)
           sh1[lqix<N>(c, n, e)] = qn[c];
           sh2[lqix<N>(c, n, e)] = r[c];
           sq[lqix<N>(c, n, e)] = qm[c];
-        } else {
-          R0[idx] = r[c];
-          q[idx] = qn[c];
         }
       }
       if constexpr (MODE == MODE_RECORD_SEG) {
@@ -443,8 +481,10 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         if (fi >= 0) {
           const int64_t r0 = (int64_t)k * TRS + f * FS + fi;
           const int64_t r1 = r0 + TRC;
-          trw[r0] = qn[0];
-          trw[r1] = nfx[f] * qn[1] + nfy[f] * qn[2] + nfz[f] * qn[3];
+          if constexpr (!TRQ) {
+            trw[r0] = qn[0];
+            trw[r1] = nfx[f] * qn[1] + nfy[f] * qn[2] + nfz[f] * qn[3];
+          }
           if (mid) {
             trm[r0] = qm[0];
             trm[r1] = nfx[f] * qm[1] + nfy[f] * qm[2] + nfz[f] * qm[3];
@@ -459,7 +499,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
 // LDS tiles left by tile_tail<..., TR2>: lane (e, g) writes face g of element e, one 16-byte store
 // per 4 face nodes (the face runs are 16-byte aligned; the padding after the last node is written
 // with zeros and never read).
-template <int N>
+template <int N, bool MID = true>
 __device__ __forceinline__ void tile_traces(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int e, int64_t m,
                                             int flag, const float *sq, const float *sqm, const float (&nfx)[4],
                                             const float (&nfy)[4], const float (&nfz)[4]) {
@@ -484,13 +524,15 @@ __device__ __forceinline__ void tile_traces(const StepArgs &a, const SlotArgs &s
         const int node = sel4(g, T.fmask[0][s], T.fmask[1][s], T.fmask[2][s], T.fmask[3][s]);
         p[u] = sq[lqix<N>(0, node, e)];
         v[u] = nx * sq[lqix<N>(1, node, e)] + ny * sq[lqix<N>(2, node, e)] + nz * sq[lqix<N>(3, node, e)];
-        pm[u] = sqm[lqix<N>(0, node, e)];
-        vm[u] = nx * sqm[lqix<N>(1, node, e)] + ny * sqm[lqix<N>(2, node, e)] + nz * sqm[lqix<N>(3, node, e)];
+        if constexpr (MID) {
+          pm[u] = sqm[lqix<N>(0, node, e)];
+          vm[u] = nx * sqm[lqix<N>(1, node, e)] + ny * sqm[lqix<N>(2, node, e)] + nz * sqm[lqix<N>(3, node, e)];
+        }
       }
     }
     *reinterpret_cast<float4 *>(trw + 4 * j) = float4{p[0], p[1], p[2], p[3]};
     *reinterpret_cast<float4 *>(trw + TRC + 4 * j) = float4{v[0], v[1], v[2], v[3]};
-    if (mid) {
+    if (MID && mid) {
       *reinterpret_cast<float4 *>(trm + 4 * j) = float4{pm[0], pm[1], pm[2], pm[3]};
       *reinterpret_cast<float4 *>(trm + TRC + 4 * j) = float4{vm[0], vm[1], vm[2], vm[3]};
     }
@@ -1090,6 +1132,13 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     DGRTM_WAIT_VM(0);
     __builtin_amdgcn_sched_barrier(0);
     const int64_t k = tile * 16 + e;
+    // neighbour entries and codes of the tile's faces: they land while the volume terms run
+    int nbv[4], cdv[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      nbv[f] = a.nbr[tix(4, f, k)];
+      cdv[f] = a.ncode[tix(4, f, k)];
+    }
     // an opaque zero keeps the operator-fragment reads inside the tile loop (hoisting them out
     // would pin every fragment in registers for the whole kernel)
     int opaque0;
@@ -1142,25 +1191,32 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
 
     // ---- surface: rp -= LIFT Pp (accumulated by the MFMA with -Pp), G_f = LIFT_f Pv, rv -= n_f G_f
     float nfx[4], nfy[4], nfz[4];
+    FaceCtx fcs[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) fcs[f] = face_ctx_of<N>(a, sl, f, gg, nbv[f], cdv[f]);
+    // the neighbour's traces at this lane's face nodes: all faces in one batch unless LEAN
+    auto nbtrace = [&](const FaceCtx &fc, int cc, float &p_, float &v_) {
+      const bool inner = fc.nb >= 0;
+      const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::FS +
+                         fc.tab[inner ? min(4 * cc + g, Nfp - 1) : 0];
+      p_ = inner ? nbt[0] : 0.0f;
+      v_ = inner ? nbt[Dm::TRC] : 0.0f;
+    };
+    float tpa[4][FC], tva[4][FC];
+    if constexpr (!LEAN) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int cc = 0; cc < FC; ++cc) nbtrace(fcs[f], cc, tpa[f][cc], tva[f][cc]);
+    }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const FaceCtx fc = face_ctx<N>(a, sl, f, k, gg);
+      const FaceCtx &fc = fcs[f];
       nfx[f] = fc.nx; nfy[f] = fc.ny; nfz[f] = fc.nz;
       // boundary states without branches (cP = 1 rigid wall, -1 free surface, 0 otherwise)
-      const bool inner = fc.nb >= 0;
       const float cP = fc.nb == -1 ? 1.0f : (fc.nb == -3 ? -1.0f : 0.0f);
-      // the neighbour's traces at this lane's face nodes (all chunks at once unless LEAN)
-      auto nbtrace = [&](int cc, float &p_, float &v_) {
-        const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::FS +
-                           fc.tab[inner ? min(4 * cc + g, Nfp - 1) : 0];
-        p_ = inner ? nbt[0] : 0.0f;
-        v_ = inner ? nbt[Dm::TRC] : 0.0f;
-      };
-      float tp[FC], tv[FC];
-      if constexpr (!LEAN) {
-#pragma unroll
-        for (int cc = 0; cc < FC; ++cc) nbtrace(cc, tp[cc], tv[cc]);
-      }
+      float (&tp)[FC] = tpa[f];
+      float (&tv)[FC] = tva[f];
       v4f G[NR];
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1172,7 +1228,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         const float pm = q_t[lqix<N>(0, node, e)];
         const float nvm = fc.nx * q_t[lqix<N>(1, node, e)] + fc.ny * q_t[lqix<N>(2, node, e)] +
                           fc.nz * q_t[lqix<N>(3, node, e)];
-        if constexpr (LEAN) nbtrace(cc, tp[cc], tv[cc]);
+        if constexpr (LEAN) nbtrace(fc, cc, tp[cc], tv[cc]);
         const float pp = cP * pm + tp[cc];
         const float nvp = -(cP * nvm + tv[cc]);
         const float dp = pp - pm, dnv = nvp - nvm;
@@ -1195,7 +1251,10 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE, true>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    tile_tail<N, MODE, true, false, false, false, MODE != MODE_RHS_ONLY>(a, sl, k, g, lev, sh, m, flag, q_t, e,
+                                                                        gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    // own-step traces of the new state (now in the state tile); the half-step ones went out per lane
+    if constexpr (MODE != MODE_RHS_ONLY) tile_traces<N, false>(a, sl, k, g, e, m, flag, q_t, nullptr, nfx, nfy, nfz);
     // every LDS read of this tile is done: the next tile's copies may land
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
