@@ -1102,6 +1102,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   constexpr bool LEAN = N >= 6;
   constexpr int VU = LEAN ? 1 : 2;
   extern __shared__ __align__(16) float sdyn[];   // [operators if OPS_LDS][4 wavefronts][QW + GW]
+  __shared__ __align__(16) uint32_t stabw[Dm::TABW];   // face-node map [4][4][6][Nfp]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = lane & 15, g = lane >> 4;
   const int64_t K = a.Ktot;
@@ -1123,6 +1124,8 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     stage_dma<4 * Dm::OPS>(a.ops, sdyn, wave, lane);
     ops = sdyn;
   }
+  stage_dma<4 * Dm::TABW>(a.nbr_index, stabw, wave, lane);
+  const int8_t *stab = reinterpret_cast<const int8_t *>(stabw);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
@@ -1197,8 +1200,10 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     // the neighbour's traces at this lane's face nodes: all faces in one batch unless LEAN
     auto nbtrace = [&](const FaceCtx &fc, int cc, float &p_, float &v_) {
       const bool inner = fc.nb >= 0;
+      // the face-node map in LDS: fc.tab points into the global copy at the same offset
+      const int8_t *tab = stab + (fc.tab - a.nbr_index);
       const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::FS +
-                         fc.tab[inner ? min(4 * cc + g, Nfp - 1) : 0];
+                         tab[inner ? min(4 * cc + g, Nfp - 1) : 0];
       p_ = inner ? nbt[0] : 0.0f;
       v_ = inner ? nbt[Dm::TRC] : 0.0f;
     };
@@ -1563,7 +1568,7 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
     constexpr size_t lds_ops = (size_t)Dims<N>::OPS * sizeof(float);
     const dim3 grid1((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
                      (unsigned)a.nslots);
-    if constexpr (lds_ops + tiles <= 160 * 1024) {
+    if constexpr (lds_ops + tiles + 4 * Dims<N>::TABW <= 160 * 1024) {
       static bool done = false;
       hipError_t e = ensure_lds(step_kernel_lowreg<N, MODE, true>, lds_ops + tiles, done);
       if (e != hipSuccess) return e;
