@@ -1112,7 +1112,11 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   float *const g_t = q_t + QW;
   const uint32_t lq = __builtin_amdgcn_readfirstlane(lds_addr(q_t));
   const uint32_t lg = lq + 4 * QW;
-  const int64_t tstride = 4 * (int64_t)gridDim.x;
+  // Tiles as in step_kernel_dma: two fixed tiles per wavefront, then (a launch with at least three
+  // tiles per wavefront) tiles handed out by the slot's counter and staggered wavefront starts
+  const int64_t nfirst = 4 * (int64_t)gridDim.x;
+  const bool dyn = ntiles >= 3 * nfirst;
+  uint32_t *const ctr = a.tile_ctr + 2 * blockIdx.y;
   int64_t tile = (int64_t)blockIdx.x * 4 + wave;
   auto issue = [&](int64_t t) {
     copy_block<16 * NK>(sl.q + t * QW, lq, lane);
@@ -1128,13 +1132,18 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   const int8_t *stab = reinterpret_cast<const int8_t *>(stabw);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  if (dyn)
+    for (int i = 0; i < wave; ++i) __builtin_amdgcn_s_sleep(127);
+  int64_t nxt = tile + nfirst;
 
-  for (; tile < ntiles; tile += tstride) {
+  while (tile < ntiles) {
     // this tile's state and geometry have landed
     __builtin_amdgcn_sched_barrier(0);
     DGRTM_WAIT_VM(0);
     __builtin_amdgcn_sched_barrier(0);
     const int64_t k = tile * 16 + e;
+    uint32_t vnn = 0u;   // the tile after the next (counter value), read at the end of this tile
+    if (dyn && nxt < ntiles && lane == 0) vnn = atomicAdd(ctr, 1u);
     // neighbour entries and codes of the tile's faces: they land while the volume terms run
     int nbv[4], cdv[4];
 #pragma unroll
@@ -1260,10 +1269,25 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
                                                                         gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
     // own-step traces of the new state (now in the state tile); the half-step ones went out per lane
     if constexpr (MODE != MODE_RHS_ONLY) tile_traces<N, false>(a, sl, k, g, e, m, flag, q_t, nullptr, nfx, nfy, nfz);
+    const int64_t nn = dyn ? 2 * nfirst + __builtin_amdgcn_readfirstlane(vnn) : nxt + nfirst;
     // every LDS read of this tile is done: the next tile's copies may land
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    if (tile + tstride < ntiles) issue(tile + tstride);
+    if (nxt < ntiles) issue(nxt);
+    tile = nxt;
+    nxt = nn;
+  }
+  if (dyn) {
+    // the last work-group to finish clears the counters for the next launch (every wavefront of a
+    // dyn launch gets here: its first tile is below W <= ntiles)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t done = atomicAdd(ctr + 1, 1u);
+      if (done + 1u == gridDim.x) {
+        ctr[0] = 0u;
+        ctr[1] = 0u;
+      }
+    }
   }
 }
 

@@ -7,7 +7,8 @@ run the benchmark's mesh:
   by one from the same state);
 - a whole shot (forward, checkpointed recompute, backward with image) with the counter hand-out
   against the same shot with every wavefront on fixed tiles: bit for bit;
-- two shots sharing every launch (two slots, two counters) against each shot alone: bit for bit.
+- two shots sharing every launch (two slots, two counters) against each shot alone: bit for bit;
+- the same fixed-tile comparison for the N >= 5 kernel on an 80k-element N = 5 mesh.
 """
 import numpy as np
 import pytest
@@ -105,3 +106,20 @@ def test_full_size_two_slots_match_alone(big):
         assert sh.state()[0] == dgrtm.PHASE_DONE
         assert np.array_equal(sh.traces().cpu().numpy(), tr)
         assert np.array_equal(sh.image().cpu().numpy(), img)
+
+
+def test_n5_counter_handout_matches_fixed_tiles():
+    from paper_1506_00907_amd import dgrtm, inputs as I
+    mm, rho, c, N = I.config_mesh("two_layer_small:28:28:17:5")
+    assert N == 5 and mm.K // 16 >= 3 * 4 * 256   # the full-prefix launches hand tiles out
+    lm = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, 3).bind("cuda")
+    spec = _spec(mm, (1.0, 1.0), 13, lm, ckpt_interval=4)
+    a = _alone(lm, spec)
+    try:
+        lm.set_launch_cap(1 << 30)
+        b = _alone(lm, spec)
+    finally:
+        lm.set_launch_cap(0)
+    assert np.abs(a[0]).max() > 0 and np.abs(a[2]).max() > 0
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
