@@ -259,7 +259,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the whole mesh and shot live on one MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding a shot or a survey over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
