@@ -559,27 +559,31 @@ __device__ __forceinline__ void volume_to_rhs(const float *gg, const v4f (&cp)[N
 }
 
 // ------------------------------------------------------------------------------------------
-// The FP32 step kernel for N <= 4.  One wavefront owns a tile of 16 consecutive elements.  The
-// element-batched operator products run on v_mfma_f32_16x16x4_f32: A = 16 operator rows x 4
-// columns (lane l holds A[l%16][l/16]), B = 4 input nodes x 16 elements (lane l holds
-// B[l/16][l%16]), C = 16 rows x 16 elements (lane l holds rows 4(l/16)+i, i=0..3, of element
-// l%16).  All elementwise work (geometric factors, penalties, AB3, traces, image) runs in that C
-// layout: lane l handles the element e = l%16 and, in row tile rt, the nodes n = 16 rt + 4 (l/16) + i.
-// The kernel is pipelined across tiles:
-//  - The volume operator fragments live in registers for the whole kernel (81 per lane at N = 4;
-//    the matrix cores read their A operand from there) and the LIFT fragments in LDS (12 KB),
-//    which leaves room in LDS for the data tiles.
+// The step kernel for N <= 4 (FP32 or split-BF16 products).  One wavefront owns a tile of 16
+// consecutive elements.  The element-batched operator products run on the matrix cores: FP32 on
+// v_mfma_f32_16x16x4_f32 with A = 16 operator rows x 4 columns (lane l holds A[l%16][l/16]),
+// B = 4 input nodes x 16 elements (lane l holds B[l/16][l%16]), C = 16 rows x 16 elements (lane
+// l holds rows 4(l/16)+i, i=0..3, of element l%16); split-BF16 on v_mfma_f32_16x16x16_bf16 with
+// 16-column chunks.  All elementwise work (geometric factors, penalties, AB3, traces, image) runs
+// in the C layout: lane l handles the element e = l%16 and, in row tile rt, the nodes
+// n = 16 rt + 4 (l/16) + i.  The kernel is pipelined across tiles:
+//  - The volume operator fragments live in registers for the whole kernel (81 per lane at N = 4
+//    in FP32, 108 in split-BF16; the matrix cores read their A operand from there) and the LIFT
+//    fragments and the face-node map in LDS (13.4 KB), which leaves room for the data tiles.
 //  - Everything a tile reads in bulk is copied HBM -> LDS by global_load_lds (no registers hold
-//    data in flight): its fields, geometric factors and the two older rhs as element-contiguous
-//    rows (16 rows of 16 elements per 16-byte instruction), and the neighbour traces as 4-byte
-//    gathers (one instruction per face, face-node chunk and component).
-//  - The copies of tile t+1 are issued as soon as tile t has finished reading the LDS tiles, in
-//    the order fields, geometry, neighbour traces, history; the tile then waits only for what it
-//    needs first, so the history arrives while the operator products run.
+//    data in flight): its state, geometry and the two older rhs as 1 KB blocks, and the
+//    neighbours' face runs as 16-byte copies (the node permutation is applied when reading).
+//  - A tile's copies go out early: its state (and, in the image step, geometry and neighbour
+//    runs) at the end of the previous tile, before that tile's block stores; in the forward and
+//    recompute steps its geometry and neighbour runs right after the previous tile's surface
+//    terms; its history at its own top, landing while the operator products run.
+//  - Launches with at least three tiles per wavefront stagger the starts of a work-group's
+//    wavefronts by about a quarter tile and hand tiles out from a counter.
 // The copies are issued from inline assembly and every wait on them is explicit: vmcnt counts
-// vector-memory instructions in issue order, so "at most n outstanding" means everything but the
-// last n issued has landed.  The compiler's own waits cover only the loads it can see (element
-// ids and flags, source data), which makes them at worst stricter in hardware, never weaker.
+// vector-memory instructions (loads and stores) in issue order, so "at most n outstanding" means
+// everything but the last n issued has landed.  The compiler's own waits cover only the loads it
+// can see (element ids and flags, source data), which makes them at worst stricter in hardware,
+// never weaker.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lds_addr(const void *p) {
   return (uint32_t)(size_t)((__attribute__((address_space(3))) const void *)p);
@@ -587,12 +591,6 @@ __device__ __forceinline__ uint32_t lds_addr(const void *p) {
 // 16 bytes per lane to LDS at lds + 16 lane (lds wave-uniform)
 __device__ __forceinline__ void lds_copy16(const void *g, uint32_t lds) {
   asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g),
-               "s"(__builtin_amdgcn_readfirstlane(lds))
-               : "memory", "m0");
-}
-// 4 bytes per lane to LDS at lds + 4 lane (lds wave-uniform)
-__device__ __forceinline__ void lds_copy4(const void *g, uint32_t lds) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(g),
                "s"(__builtin_amdgcn_readfirstlane(lds))
                : "memory", "m0");
 }
@@ -663,9 +661,6 @@ struct DmaDims {
   static constexpr int GW = kGeo * 16;               // geometry tile
   static constexpr int FS = Dims<N>::FS;
   static constexpr int TW = 8 * 16 * FS;             // neighbour face runs [face][p, n.v][FS/4][16][4]
-  static constexpr int NQ = QW / 256;                // 1 KB copies of a tile's state
-  static constexpr int NG = (kGeo + 15) / 16;        // ... of the geometry tile
-  static constexpr int NT = 8;                       // 16-byte copies of the neighbour face runs
   static constexpr int WAVE = QW + GW + TW + 2 * QW;  // LDS words per wavefront
 };
 
