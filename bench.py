@@ -56,9 +56,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, mode_name: str):
+def load_traffic(workload: str, mode_name: str, profiles_dir: str = os.path.join(ROOT, "profiles")):
     """HBM bytes per launch from committed rocprofv3 PMC runs, if taken on the current kernel."""
-    p = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_traffic.json")
+    p = os.path.join(profiles_dir, f"step_kernel_{workload}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -181,7 +181,7 @@ def log(msg: str):
 
 
 def traffic_from_pmc(workload: str, fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
-                     command: str) -> str:
+                     command: str, profiles_dir: str = os.path.join(ROOT, "profiles")) -> str:
     """HBM bytes per step-kernel launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
     dispatch), each scaled by what the same counter reads for a device copy of known size, averaged
     over the launches of each step mode like the roofline's achieved figure.  Writes the JSON that
@@ -224,7 +224,7 @@ def traffic_from_pmc(workload: str, fetch_dir: str, write_dir: str, copy_fetch_d
            "copy_calibration": {"bytes": 2 ** 30, "FETCH_SIZE_KiB": kf, "WRITE_SIZE_KiB": kw,
                                 "fetch_scale": sf, "write_scale": sw},
            "command": command, "modes": modes}
-    path = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_traffic.json")
+    path = os.path.join(profiles_dir, f"step_kernel_{workload}_traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     return path
