@@ -84,27 +84,6 @@ constexpr double kCm[3][3] = {{3341.0 / 10080.0, -667.0 / 5040.0, 43.0 / 1120.0}
 
 // Copy nwords 32-bit words from global to LDS with the whole work-group: all 16-byte loads of a
 // thread are issued before its LDS stores, so the copy costs one memory latency.
-template <int NWORDS>
-__device__ __forceinline__ void stage_to_lds(const void *src, void *dst) {
-  constexpr int NV = NWORDS / 4, PER = (NV + 255) / 256;
-  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-  uint4 buf[PER];
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int i = threadIdx.x + 256 * j;
-    if (i < NV) buf[j] = s4[i];
-  }
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int i = threadIdx.x + 256 * j;
-    if (i < NV) d4[i] = buf[j];
-  }
-  const uint32_t *s1 = reinterpret_cast<const uint32_t *>(src);
-  uint32_t *d1 = reinterpret_cast<uint32_t *>(dst);
-  for (int i = 4 * NV + threadIdx.x; i < NWORDS; i += 256) d1[i] = s1[i];
-}
-
 __device__ __forceinline__ int level_of(const int64_t *lev_begin, int L, int64_t k) {
   // segments are stored finest first, so starts decrease with the level number
   for (int l = 1; l < L; ++l)
@@ -177,41 +156,6 @@ __device__ __forceinline__ FaceCtx face_ctx_of(const StepArgs &a, const SlotArgs
     c.tab = a.nbr_index + ((f * 4 + c.f2) * 6 + perm) * Nfp;
   }
   return c;
-}
-
-template <int N>
-__device__ __forceinline__ FaceCtx face_ctx(const StepArgs &a, const SlotArgs &sl, int f, int64_t k, const float *gg) {
-  return face_ctx_of<N>(a, sl, f, gg, a.nbr[tix(4, f, k)], a.ncode[tix(4, f, k)]);
-}
-
-// Penalty terms at face node s (volume node `node`) of the lane's element, already scaled by
-// J_f/J: returns -P^p and the scalar part of P^v (P^{v_i} = n_i * Pv).
-template <int N>
-__device__ __forceinline__ void penalty(const StepArgs &a, const float *q, const FaceCtx &c, int s, int node, int64_t k,
-                                        float rc2, float irho, float &mPp, float &Pv) {
-  constexpr int Np = Dims<N>::Np, Nfp = Dims<N>::Nfp, F = Dims<N>::F;
-  const int64_t K = a.Ktot;
-  constexpr int NQ4 = node_quads(Np);
-  const float pm = q[qix(NQ4, 0, node, k)];
-  const float nvm = c.nx * q[qix(NQ4, 1, node, k)] + c.ny * q[qix(NQ4, 2, node, k)] + c.nz * q[qix(NQ4, 3, node, k)];
-  float pp, nvp;
-  if (c.nb >= 0) {
-    const float *nbt = c.trp + (int64_t)c.nb * Dims<N>::TRS + c.f2 * Dims<N>::FS + c.tab[s];
-    pp = nbt[0];
-    nvp = -nbt[Dims<N>::TRC];  // n- . v+ = -(n+ . v+)
-  } else if (c.nb == -1) {  // rigid wall
-    pp = pm;
-    nvp = -nvm;
-  } else if (c.nb == -2) {  // transparent
-    pp = 0.0f;
-    nvp = 0.0f;
-  } else {  // free surface
-    pp = -pm;
-    nvp = nvm;
-  }
-  const float dp = pp - pm, dnv = nvp - nvm;
-  mPp = -0.5f * rc2 * (dnv - c.taup * dp) * c.Fs;
-  Pv = 0.5f * irho * (dp - c.tauv * dnv) * c.Fs;
 }
 
 // Everything after the operator products, in the MFMA C layout (lane: element e, rows
@@ -1081,17 +1025,20 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   }
 }
 
-// The FP32 step kernel for N >= 5, with the tile mapping and MFMA layout of step_kernel_dma.  Its
-// operators (in LDS when they fit, else read through the caches) leave room in LDS for one tile
-// per wavefront, but not for the neighbour runs and the history: each wavefront's state and
-// geometry tiles come by LDS copies, issued for the next tile as soon as the update has read the
-// state; neighbour traces and the older rhs are read per lane.
-template <int N, int MODE, bool OPS_LDS>
+// The step kernel for N >= 5 (FP32 or split-BF16 products), with the tile mapping and MFMA
+// layout of step_kernel_dma.  Its operators (in LDS when they fit, else read through the caches)
+// leave room in LDS for one tile per wavefront, but not for the neighbour runs and the history:
+// each wavefront's state and geometry tiles come by LDS copies, issued for the next tile as soon
+// as the update has read the state; neighbour traces and the older rhs are read per lane.
+template <int N, int MODE, bool OPS_LDS, int PREC>
 __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   constexpr Tab<N> T{};
   using Dm = Dims<N>;
   using DD = DmaDims<N>;
+  using DB = DimsB<N>;
   constexpr int Np = Dm::Np, Nfp = Dm::Nfp, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
+  // operator fragment floats: FP32 [3][NR][NK][64] + [NR][4 FC][64], split-BF16 the same in uint4
+  constexpr int OPSW = PREC ? DB::OPS_U4 * 4 : Dm::OPS;
   constexpr int QW = DD::QW, GW = DD::GW;
   // N = 6 has no registers to spare: one volume chunk at a time, neighbour traces read per chunk
   constexpr bool LEAN = N >= 6;
@@ -1103,7 +1050,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
   const SlotArgs &sl = a.slot[blockIdx.y];
-  float *const q_t = sdyn + (OPS_LDS ? Dm::OPS : 0) + wave * (QW + GW);
+  float *const q_t = sdyn + (OPS_LDS ? OPSW : 0) + wave * (QW + GW);
   float *const g_t = q_t + QW;
   const uint32_t lq = __builtin_amdgcn_readfirstlane(lds_addr(q_t));
   const uint32_t lg = lq + 4 * QW;
@@ -1118,9 +1065,9 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     copy_block<kGeo>(a.geo + tix(kGeo, 0, t * 16), lg, lane);
   };
   if (tile < ntiles) issue(tile);
-  const float *ops = a.ops;
+  const float *ops = PREC ? reinterpret_cast<const float *>(a.ops_bf16) : a.ops;
   if constexpr (OPS_LDS) {
-    stage_dma<4 * Dm::OPS>(a.ops, sdyn, wave, lane);
+    stage_dma<4 * OPSW>(ops, sdyn, wave, lane);
     ops = sdyn;
   }
   stage_dma<4 * Dm::TABW>(a.nbr_index, stabw, wave, lane);
@@ -1152,6 +1099,8 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
     const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
     const float *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;    // [NR][4*FC][64]
+    const uint4 *__restrict__ bD = reinterpret_cast<const uint4 *>(ops) + opaque0;          // split-BF16
+    const uint4 *__restrict__ bL = bD + 3 * NR * DB::NK * 64;
     const int flag = sl.eflag[k];
     const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
     const int sh = a.L - lev;
@@ -1168,29 +1117,67 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     v4f cp[NR], w0[NR], w1[NR], w2[NR];
 #pragma unroll
     for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+    if constexpr (PREC == 0) {
 #pragma unroll VU
-    for (int c = 0; c < NK; ++c) {
-      const int mm = 4 * c + g;
-      const bool ok = mm < Np;
-      const int mr = ok ? mm : 0;
-      const float p = ok ? q_t[lqix<N>(0, mr, e)] : 0.f;
-      const float vx = ok ? q_t[lqix<N>(1, mr, e)] : 0.f;
-      const float vy = ok ? q_t[lqix<N>(2, mr, e)] : 0.f;
-      const float vz = ok ? q_t[lqix<N>(3, mr, e)] : 0.f;
-      const float Ur = rx * vx + ry * vy + rz * vz;
-      const float Us = sx * vx + sy * vy + sz * vz;
-      const float Ut = tx * vx + ty * vy + tz * vz;
+      for (int c = 0; c < NK; ++c) {
+        const int mm = 4 * c + g;
+        const bool ok = mm < Np;
+        const int mr = ok ? mm : 0;
+        const float p = ok ? q_t[lqix<N>(0, mr, e)] : 0.f;
+        const float vx = ok ? q_t[lqix<N>(1, mr, e)] : 0.f;
+        const float vy = ok ? q_t[lqix<N>(2, mr, e)] : 0.f;
+        const float vz = ok ? q_t[lqix<N>(3, mr, e)] : 0.f;
+        const float Ur = rx * vx + ry * vy + rz * vz;
+        const float Us = sx * vx + sy * vy + sz * vz;
+        const float Ut = tx * vx + ty * vy + tz * vz;
 #pragma unroll
-      for (int rt = 0; rt < NR; ++rt) {
-        const float ar = fD[((0 * NR + rt) * NK + c) * 64 + lane];
-        const float as = fD[((1 * NR + rt) * NK + c) * 64 + lane];
-        const float at = fD[((2 * NR + rt) * NK + c) * 64 + lane];
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, Ur, cp[rt], 0, 0, 0);
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, Us, cp[rt], 0, 0, 0);
-        cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Ut, cp[rt], 0, 0, 0);
-        w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, p, w0[rt], 0, 0, 0);
-        w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, p, w1[rt], 0, 0, 0);
-        w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, p, w2[rt], 0, 0, 0);
+        for (int rt = 0; rt < NR; ++rt) {
+          const float ar = fD[((0 * NR + rt) * NK + c) * 64 + lane];
+          const float as = fD[((1 * NR + rt) * NK + c) * 64 + lane];
+          const float at = fD[((2 * NR + rt) * NK + c) * 64 + lane];
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, Ur, cp[rt], 0, 0, 0);
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, Us, cp[rt], 0, 0, 0);
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Ut, cp[rt], 0, 0, 0);
+          w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, p, w0[rt], 0, 0, 0);
+          w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, p, w1[rt], 0, 0, 0);
+          w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, p, w2[rt], 0, 0, 0);
+        }
+      }
+    } else {
+      // lane (e, g) supplies B rows 16 c + 4 g .. + 3: node quad 4 c + g of each field
+#pragma unroll VU
+      for (int c = 0; c < DB::NK; ++c) {
+        const int qd = 4 * c + g;
+        const bool ok = 4 * c + 3 < NK || qd < NK;
+        const int qr = ok ? qd : 0;
+        float4 p4 = *reinterpret_cast<const float4 *>(&q_t[lqix<N>(0, 4 * qr, e)]);
+        float4 x4 = *reinterpret_cast<const float4 *>(&q_t[lqix<N>(1, 4 * qr, e)]);
+        float4 y4 = *reinterpret_cast<const float4 *>(&q_t[lqix<N>(2, 4 * qr, e)]);
+        float4 z4 = *reinterpret_cast<const float4 *>(&q_t[lqix<N>(3, 4 * qr, e)]);
+        if (!ok) p4 = x4 = y4 = z4 = float4{0.f, 0.f, 0.f, 0.f};
+        const float pv[4] = {p4.x, p4.y, p4.z, p4.w}, xv[4] = {x4.x, x4.y, x4.z, x4.w};
+        const float yv[4] = {y4.x, y4.y, y4.z, y4.w}, zv[4] = {z4.x, z4.y, z4.z, z4.w};
+        v4s urh, url, ush, usl, uth, utl, ph, pl;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          short h, l;
+          split_bf16(rx * xv[v] + ry * yv[v] + rz * zv[v], h, l); urh[v] = h; url[v] = l;
+          split_bf16(sx * xv[v] + sy * yv[v] + sz * zv[v], h, l); ush[v] = h; usl[v] = l;
+          split_bf16(tx * xv[v] + ty * yv[v] + tz * zv[v], h, l); uth[v] = h; utl[v] = l;
+          split_bf16(pv[v], h, l); ph[v] = h; pl[v] = l;
+        }
+#pragma unroll
+        for (int rt = 0; rt < NR; ++rt) {
+          const uint4 ar = bD[((0 * NR + rt) * DB::NK + c) * 64 + lane];
+          const uint4 as = bD[((1 * NR + rt) * DB::NK + c) * 64 + lane];
+          const uint4 at = bD[((2 * NR + rt) * DB::NK + c) * 64 + lane];
+          DGRTM_MF3(ar, urh, url, cp[rt]);
+          DGRTM_MF3(as, ush, usl, cp[rt]);
+          DGRTM_MF3(at, uth, utl, cp[rt]);
+          DGRTM_MF3(ar, ph, pl, w0[rt]);
+          DGRTM_MF3(as, ph, pl, w1[rt]);
+          DGRTM_MF3(at, ph, pl, w2[rt]);
+        }
       }
     }
     v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
@@ -1212,7 +1199,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       v_ = inner ? nbt[Dm::TRC] : 0.0f;
     };
     float tpa[4][FC], tva[4][FC];
-    if constexpr (!LEAN) {
+    if constexpr (!LEAN && PREC == 0) {
 #pragma unroll
       for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -1229,25 +1216,61 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       v4f G[NR];
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+      if constexpr (PREC == 0) {
 #pragma unroll
-      for (int cc = 0; cc < FC; ++cc) {
-        const bool sv = 4 * cc + 3 < Nfp || 4 * cc + g < Nfp;   // face node 4 cc + g exists
-        const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
-                              T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
-        const float pm = q_t[lqix<N>(0, node, e)];
-        const float nvm = fc.nx * q_t[lqix<N>(1, node, e)] + fc.ny * q_t[lqix<N>(2, node, e)] +
-                          fc.nz * q_t[lqix<N>(3, node, e)];
-        if constexpr (LEAN) nbtrace(fc, cc, tp[cc], tv[cc]);
-        const float pp = cP * pm + tp[cc];
-        const float nvp = -(cP * nvm + tv[cc]);
-        const float dp = pp - pm, dnv = nvp - nvm;
-        const float mPp = sv ? -0.5f * rc2 * (dnv - fc.taup * dp) * fc.Fs : 0.0f;
-        const float Pv = sv ? 0.5f * irho * (dp - fc.tauv * dnv) * fc.Fs : 0.0f;
+        for (int cc = 0; cc < FC; ++cc) {
+          const bool sv = 4 * cc + 3 < Nfp || 4 * cc + g < Nfp;   // face node 4 cc + g exists
+          const int node = sel4(g, T.fmask[f][4 * cc], T.fmask[f][min(4 * cc + 1, Nfp - 1)],
+                                T.fmask[f][min(4 * cc + 2, Nfp - 1)], T.fmask[f][min(4 * cc + 3, Nfp - 1)]);
+          const float pm = q_t[lqix<N>(0, node, e)];
+          const float nvm = fc.nx * q_t[lqix<N>(1, node, e)] + fc.ny * q_t[lqix<N>(2, node, e)] +
+                            fc.nz * q_t[lqix<N>(3, node, e)];
+          if constexpr (LEAN) nbtrace(fc, cc, tp[cc], tv[cc]);
+          const float pp = cP * pm + tp[cc];
+          const float nvp = -(cP * nvm + tv[cc]);
+          const float dp = pp - pm, dnv = nvp - nvm;
+          const float mPp = sv ? -0.5f * rc2 * (dnv - fc.taup * dp) * fc.Fs : 0.0f;
+          const float Pv = sv ? 0.5f * irho * (dp - fc.tauv * dnv) * fc.Fs : 0.0f;
 #pragma unroll
-        for (int rt = 0; rt < NR; ++rt) {
-          const float al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
-          rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
-          G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
+          for (int rt = 0; rt < NR; ++rt) {
+            const float al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
+            rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
+            G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
+          }
+        }
+      } else {
+        const bool inner = fc.nb >= 0;
+        const int8_t *tab = stab + (fc.tab - a.nbr_index);
+#pragma unroll
+        for (int cc = 0; cc < DB::FC; ++cc) {   // lane (e, g) takes face nodes 16 cc + 4 g + v
+          v4s pph, ppl, pvh, pvl;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int s = 16 * cc + 4 * g + v;
+            const bool sv = 16 * cc + 12 + v < Nfp || s < Nfp;
+            const int node = sel4(g, T.fmask[f][min(16 * cc + v, Nfp - 1)], T.fmask[f][min(16 * cc + 4 + v, Nfp - 1)],
+                                  T.fmask[f][min(16 * cc + 8 + v, Nfp - 1)], T.fmask[f][min(16 * cc + 12 + v, Nfp - 1)]);
+            const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::FS +
+                               tab[inner ? min(s, Nfp - 1) : 0];
+            const float tps = inner ? nbt[0] : 0.0f, tvs = inner ? nbt[Dm::TRC] : 0.0f;
+            const float pm = q_t[lqix<N>(0, node, e)];
+            const float nvm = fc.nx * q_t[lqix<N>(1, node, e)] + fc.ny * q_t[lqix<N>(2, node, e)] +
+                              fc.nz * q_t[lqix<N>(3, node, e)];
+            const float pp = cP * pm + tps;
+            const float nvp = -(cP * nvm + tvs);
+            const float dp = pp - pm, dnv = nvp - nvm;
+            const float mPp = sv ? -0.5f * rc2 * (dnv - fc.taup * dp) * fc.Fs : 0.0f;
+            const float Pv = sv ? 0.5f * irho * (dp - fc.tauv * dnv) * fc.Fs : 0.0f;
+            short h, l;
+            split_bf16(mPp, h, l); pph[v] = h; ppl[v] = l;
+            split_bf16(Pv, h, l); pvh[v] = h; pvl[v] = l;
+          }
+#pragma unroll
+          for (int rt = 0; rt < NR; ++rt) {
+            const uint4 al = bL[(rt * 4 * DB::FC + f * DB::FC + cc) * 64 + lane];
+            DGRTM_MF3(al, pph, ppl, rp[rt]);
+            DGRTM_MF3(al, pvh, pvl, G[rt]);
+          }
         }
       }
 #pragma unroll
@@ -1283,130 +1306,6 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         ctr[1] = 0u;
       }
     }
-  }
-}
-
-template <int N, int MODE, bool OPS_LDS>
-__global__ __launch_bounds__(256) void step_kernel_bf16(const StepArgs a) {
-  constexpr Tab<N> T{};
-  using Dm = DimsB<N>;
-  constexpr int Np = Dm::Np, Nfp = Dm::Nfp, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
-  extern __shared__ uint4 sopsb[];
-  const uint4 *ops = reinterpret_cast<const uint4 *>(a.ops_bf16);
-  if constexpr (OPS_LDS) {
-    stage_to_lds<Dm::OPS_U4 * 4>(ops, sopsb);
-    __syncthreads();
-    ops = sopsb;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int e = lane & 15, g = lane >> 4;
-  const int64_t K = a.Ktot;
-  const int64_t ntiles = a.k_end >> 4;
-  const SlotArgs &sl = a.slot[blockIdx.y];
-  auto hi = [](const uint4 &u) { return __builtin_bit_cast(v4s, uint2{u.x, u.y}); };
-  auto lo = [](const uint4 &u) { return __builtin_bit_cast(v4s, uint2{u.z, u.w}); };
-
-  for (int64_t grp = blockIdx.x; grp * 4 < ntiles; grp += gridDim.x) {
-    const int64_t tile = grp * 4 + wave;
-    if (tile >= ntiles) continue;
-    const int64_t k = tile * 16 + e;
-    int opaque0;
-    asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
-    const uint4 *__restrict__ fD = ops + opaque0;                      // [3][NR][NK][64]
-    const uint4 *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;   // [NR][4*FC][64]
-    const int flag = sl.eflag[k];
-    const int lev = level_of(a.lev_begin, a.L, tile * 16);
-    const int sh = a.L - lev;
-    const int64_t m = sl.tau >> sh;
-    float gg[kGeo];
-#pragma unroll
-    for (int i = 0; i < kGeo; ++i) gg[i] = a.geo[tix(kGeo, i, k)];
-    const float rx = gg[0], ry = gg[1], rz = gg[2], sx = gg[3], sy = gg[4], sz = gg[5], tx = gg[6], ty = gg[7],
-                tz = gg[8];
-    const float rc2 = gg[9], irho = gg[10];
-
-    v4f cp[NR], w0[NR], w1[NR], w2[NR];
-#pragma unroll
-    for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-    for (int c = 0; c < NK; ++c) {
-      v4s urh, url, ush, usl, uth, utl, ph, pl;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int mm = 16 * c + 4 * g + v;
-        float p = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
-        if (mm < Np) {
-          p = sl.q[qix(node_quads(Np), 0, mm, k)];
-          vx = sl.q[qix(node_quads(Np), 1, mm, k)];
-          vy = sl.q[qix(node_quads(Np), 2, mm, k)];
-          vz = sl.q[qix(node_quads(Np), 3, mm, k)];
-        }
-        short h, l;
-        split_bf16(rx * vx + ry * vy + rz * vz, h, l); urh[v] = h; url[v] = l;
-        split_bf16(sx * vx + sy * vy + sz * vz, h, l); ush[v] = h; usl[v] = l;
-        split_bf16(tx * vx + ty * vy + tz * vz, h, l); uth[v] = h; utl[v] = l;
-        split_bf16(p, h, l); ph[v] = h; pl[v] = l;
-      }
-#pragma unroll
-      for (int rt = 0; rt < NR; ++rt) {
-        const uint4 ar = fD[((0 * NR + rt) * NK + c) * 64 + lane];
-        const uint4 as = fD[((1 * NR + rt) * NK + c) * 64 + lane];
-        const uint4 at = fD[((2 * NR + rt) * NK + c) * 64 + lane];
-#define MF(A, B, C) C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, C, 0, 0, 0)
-        MF(hi(ar), urh, cp[rt]); MF(hi(ar), url, cp[rt]); MF(lo(ar), urh, cp[rt]);
-        MF(hi(as), ush, cp[rt]); MF(hi(as), usl, cp[rt]); MF(lo(as), ush, cp[rt]);
-        MF(hi(at), uth, cp[rt]); MF(hi(at), utl, cp[rt]); MF(lo(at), uth, cp[rt]);
-        MF(hi(ar), ph, w0[rt]); MF(hi(ar), pl, w0[rt]); MF(lo(ar), ph, w0[rt]);
-        MF(hi(as), ph, w1[rt]); MF(hi(as), pl, w1[rt]); MF(lo(as), ph, w1[rt]);
-        MF(hi(at), ph, w2[rt]); MF(hi(at), pl, w2[rt]); MF(lo(at), ph, w2[rt]);
-      }
-    }
-    v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
-    volume_to_rhs<NR>(gg, cp, w0, w1, w2, rp, rvx, rvy, rvz);
-
-    float nfx[4], nfy[4], nfz[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const FaceCtx fc = face_ctx<N>(a, sl, f, k, gg);
-      nfx[f] = fc.nx; nfy[f] = fc.ny; nfz[f] = fc.nz;
-      v4f G[NR];
-#pragma unroll
-      for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int cc = 0; cc < FC; ++cc) {
-        v4s pph, ppl, pvh, pvl;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int s = 16 * cc + 4 * g + v;
-          float mPp = 0.f, Pv = 0.f;
-          if (16 * cc + 12 + v < Nfp || s < Nfp) {
-            const int node = sel4(g, T.fmask[f][min(16 * cc + v, Nfp - 1)], T.fmask[f][min(16 * cc + 4 + v, Nfp - 1)],
-                                  T.fmask[f][min(16 * cc + 8 + v, Nfp - 1)], T.fmask[f][min(16 * cc + 12 + v, Nfp - 1)]);
-            penalty<N>(a, sl.q, fc, s, node, k, rc2, irho, mPp, Pv);
-          }
-          short h, l;
-          split_bf16(mPp, h, l); pph[v] = h; ppl[v] = l;
-          split_bf16(Pv, h, l); pvh[v] = h; pvl[v] = l;
-        }
-#pragma unroll
-        for (int rt = 0; rt < NR; ++rt) {
-          const uint4 al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
-          MF(hi(al), pph, rp[rt]); MF(hi(al), ppl, rp[rt]); MF(lo(al), pph, rp[rt]);
-          MF(hi(al), pvh, G[rt]); MF(hi(al), pvl, G[rt]); MF(lo(al), pvh, G[rt]);
-#undef MF
-        }
-      }
-#pragma unroll
-      for (int rt = 0; rt < NR; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          rvx[rt][i] -= fc.nx * G[rt][i];
-          rvy[rt][i] -= fc.ny * G[rt][i];
-          rvz[rt][i] -= fc.nz * G[rt][i];
-        }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    tile_tail<N, MODE>(a, sl, k, g, lev, sh, m, flag, nullptr, e, gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
   }
 }
 
@@ -1541,16 +1440,6 @@ __global__ void fill_f64_kernel(double *p, int64_t n, double v) {
 // ------------------------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <class KernelFn>
-static hipError_t ensure_lds(KernelFn fn, size_t lds, bool &done) {
-  if (lds > 64 * 1024 && !done) {
-    hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  done = true;
-  return hipSuccess;
-}
-
 static int64_t device_cus() {
   static int64_t cus = 0;
   if (cus == 0) {
@@ -1567,37 +1456,26 @@ template <int N, int MODE>
 static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
   const int64_t groups = (a.k_end / 16 + 3) / 4;
   if constexpr (N >= 5) {
-    // a persistent-style grid: each work-group stages the operators once and then takes tile groups
-    const int64_t cap = a.max_groups > 0 ? a.max_groups : 2 * device_cus();
-    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(groups, cap)), (unsigned)a.nslots), block(256);
-    if (a.precision == 1) {
-      constexpr size_t lds = (size_t)DimsB<N>::OPS_U4 * sizeof(uint4);
-      if constexpr (lds <= 96 * 1024) {
-        static bool done = false;
-        hipError_t e = ensure_lds(step_kernel_bf16<N, MODE, true>, lds, done);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((step_kernel_bf16<N, MODE, true>), grid, block, lds, st, a);
-      } else {
-        hipLaunchKernelGGL((step_kernel_bf16<N, MODE, false>), grid, block, 0, st, a);
-      }
-      return hipGetLastError();
-    }
-    // one work-group per CU: the operators (when they fit) and one state tile per wavefront
+    // one work-group per CU: the operators (when they fit), the face-node map and one state tile
+    // per wavefront
     constexpr size_t tiles = (size_t)4 * (DmaDims<N>::QW + DmaDims<N>::GW) * sizeof(float);
-    constexpr size_t lds_ops = (size_t)Dims<N>::OPS * sizeof(float);
+    constexpr size_t map = (size_t)4 * Dims<N>::TABW;
+    constexpr size_t ops32 = (size_t)Dims<N>::OPS * sizeof(float);
+    constexpr size_t opsb = (size_t)DimsB<N>::OPS_U4 * sizeof(uint4);
     const dim3 grid1((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
-                     (unsigned)a.nslots);
-    if constexpr (lds_ops + tiles + 4 * Dims<N>::TABW <= 160 * 1024) {
-      static bool done = false;
-      hipError_t e = ensure_lds(step_kernel_lowreg<N, MODE, true>, lds_ops + tiles, done);
+                     (unsigned)a.nslots), block(256);
+    auto go = [&](auto kern, size_t lds) -> hipError_t {
+      hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, true>), grid1, block, lds_ops + tiles, st, a);
-    } else {
-      static bool done = false;
-      hipError_t e = ensure_lds(step_kernel_lowreg<N, MODE, false>, tiles, done);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((step_kernel_lowreg<N, MODE, false>), grid1, block, tiles, st, a);
+      hipLaunchKernelGGL(kern, grid1, block, lds, st, a);
+      return hipGetLastError();
+    };
+    if (a.precision == 1) {
+      if constexpr (opsb + tiles + map <= 160 * 1024) return go(step_kernel_lowreg<N, MODE, true, 1>, opsb + tiles);
+      else return go(step_kernel_lowreg<N, MODE, false, 1>, tiles);
     }
+    if constexpr (ops32 + tiles + map <= 160 * 1024) return go(step_kernel_lowreg<N, MODE, true, 0>, ops32 + tiles);
+    else return go(step_kernel_lowreg<N, MODE, false, 0>, tiles);
   } else {
     // one work-group per CU (its static LDS fills the CU); each loops over tiles.  A launch with
     // fewer than two tiles per wavefront of a full grid takes a smaller grid with two tiles per
