@@ -3,8 +3,8 @@
 Requests (a mesh, a source position, a Ricker frequency) arrive over time.  The server
 keeps every admitted shot's wavefields, checkpoints and image resident in HBM, admits a
 waiting request as soon as a slot and memory are free (admission by the shot's exact
-workspace footprint), and advances all running shots of a mesh together: shots of one mesh
-at the same step mode share each kernel launch (dgrtm_step_shots).  Each mesh has its own
+workspace footprint and a per-mesh slot limit), and advances all running shots of a mesh
+together: shots of one mesh at the same step mode share each kernel launch (dgrtm_step_shots).  Each mesh has its own
 stream, so shots on different meshes overlap on the device.  A request that arrives while
 others run joins at the next tick, at a global-step boundary.
 
@@ -131,10 +131,11 @@ class ServeResult:
                 "latency_p99_s": round(float(np.percentile(lat, 99)), 3)}
 
 
-def serve_batched(pools: dict, requests: list[Request], hbm_budget: int, max_slots: int = 8,
+def serve_batched(pools: dict, requests: list[Request], hbm_budget: int, max_slots=8,
                   steps_per_tick: int = 16, results: dict | None = None, clock=time.perf_counter,
                   sleep=time.sleep, log=None) -> ServeResult:
     """Continuous batching: admit as slots/memory free up; advance every running shot each tick.
+    `max_slots`: shots running at once on one mesh (an int, or a dict mesh -> int).
     `log(msg)`, if given, is called when a request completes."""
     pending = sorted(requests, key=lambda r: r.arrival)
     waiting: list[Request] = []
@@ -153,7 +154,8 @@ def serve_batched(pools: dict, requests: list[Request], hbm_budget: int, max_slo
             fp = pool.footprint(req)
             if fp > hbm_budget:
                 raise ValueError(f"request {req.rid} needs {fp} bytes, more than the budget")
-            if len(pool.running) < max_slots and used + fp <= hbm_budget:
+            limit = max_slots.get(req.mesh, 1) if isinstance(max_slots, dict) else max_slots
+            if len(pool.running) < limit and used + fp <= hbm_budget:
                 shot = pool.new_shot(req)
                 used += fp
                 req.admitted = clock() - t0
