@@ -81,7 +81,9 @@ const char *dgrtm_last_error(void);
  *   vert_xyz   host, n_vert x 3 doubles
  *   elem_vert  host, n_elem x 4 vertex indices; elements with negative volume are re-oriented
  *   face_bc    host, n_elem x 4 boundary types (DGRTM_BC_*) read on boundary faces only, or
- *              NULL to use bc_default everywhere
+ *              NULL to use bc_default everywhere.  Face f of element k is numbered on the
+ *              re-oriented element (vertices 2 and 3 swapped where the volume was negative):
+ *              faces 0..3 are its local vertex triples (0,1,2), (0,1,3), (1,2,3), (0,2,3)
  * Host work only.  Errors: DGRTM_ERR_ARG, DGRTM_ERR_MESH.
  */
 dgrtm_status dgrtm_mesh_create(int N, int64_t n_vert, const double *vert_xyz, int64_t n_elem,

@@ -122,6 +122,58 @@ def test_rtm_image_parity(cond, ckpt):
     assert rel(img, img_ref) < 1e-4
 
 
+def _top_free_face_bc(mm, nx, ny):
+    """Free surface (p = 0) on the faces in the top plane z = Lz, transparent elsewhere; faces
+    numbered on the re-oriented element, as the library and the oracle both read them."""
+    from oracle.mesh import orient
+    from oracle.refelem import FACE_VERTS
+    verts = np.asarray(mm.verts, dtype=np.float64)
+    et = orient(verts, np.asarray(mm.etov, dtype=np.int64))
+    bc = np.full((mm.K, 4), BC_TRANSPARENT, dtype=np.int8)
+    for f, lv in enumerate(FACE_VERTS):
+        on_top = np.all(np.abs(verts[et[:, list(lv)], 2] - mm.box[2]) < 1e-12, axis=1)
+        bc[on_top, f] = BC_FREE
+    assert (bc == BC_FREE).sum() == 2 * nx * ny      # two triangles per top cell
+    return bc
+
+
+@pytest.mark.parametrize("up", [(0.0, 0.0, 1.0), (0.5, 0.0, 0.8660254037844386)])
+def test_free_surface_top_oblique_up_and_stacked_image(up):
+    """A free-surface top boundary, a vertical or an oblique characteristic direction, and two
+    shots stacked into one image through the accumulate form of dgrtm_image."""
+    from oracle.dg import Operator
+    from paper_1506_00907_amd import dgrtm
+    name = "two_layer_small:6:6:4:2"
+    mm, rho, c, N = I.config_mesh(name)
+    bc = _top_free_face_bc(mm, 6, 6)
+    lm = dgrtm.Mesh(N, mm.verts, mm.etov, face_bc=bc).set_model(rho, c, n_levels_max=3).bind("cuda")
+    om = OMesh(get_ref(N), mm.verts, mm.etov, face_bc=bc)
+    op = Operator(om, rho, c)
+    lev, L, dtl = lts_levels(local_dt(om.verts, om.etov, c, N), om.EToE, 3)
+    assert L == lm.L and L >= 2
+    ng = 30
+    stack = torch.zeros((lm.K, lm.Np), dtype=torch.float64, device="cuda")
+    imgs, refs = [], []
+    for src_xy in [(0.7797, 1.0), (1.3, 0.6)]:
+        spec = I.rtm_shot(src_xy=src_xy, n_rec=4)
+        spec.t_peak = 0.03
+        shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=ng * dtl * 2 ** (L - 1), src=spec.src, f_peak=spec.f_peak,
+                                             t_peak=spec.t_peak, rec=spec.rec, ckpt_interval=4))
+        tr = shot.forward()
+        shot.adjoint(tr, condition=dgrtm.IMAGE_CHARACTERISTIC, up=up, g_image_start=4)
+        imgs.append(shot.image().cpu().numpy())
+        shot.image(out=stack, accumulate=True)
+        osh = oracle_shot(op, lev, L, dtl, ng, spec)
+        tr_ref = osh.forward(condition=COND_CHARACTERISTIC, up=up)
+        assert rel(tr.cpu().numpy(), tr_ref) < 1e-5
+        refs.append(osh.adjoint(tr.cpu().numpy().astype(np.float64), condition=COND_CHARACTERISTIC, up=up,
+                                g_image_start=4))
+        assert rel(imgs[-1], refs[-1]) < 1e-4
+    stack = stack.cpu().numpy()
+    assert np.array_equal(stack, imgs[0] + imgs[1])
+    assert rel(stack, refs[0] + refs[1]) < 1e-4
+
+
 def test_residual_fp64():
     from paper_1506_00907_amd import dgrtm
     lm, *_ = lib_mesh("two_layer_small:2:2:2:1", BC_TRANSPARENT, 1)
