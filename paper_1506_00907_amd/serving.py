@@ -4,8 +4,9 @@ Requests (a mesh, a source position, a Ricker frequency) arrive over time.  The 
 keeps every admitted shot's wavefields, checkpoints and image resident in HBM, admits a
 waiting request as soon as a slot and memory are free (admission by the shot's exact
 workspace footprint and a per-mesh slot limit), and advances all running shots of a mesh
-together: shots of one mesh at the same step mode share each kernel launch (dgrtm_step_shots).  Each mesh has its own
-stream, so shots on different meshes overlap on the device.  A request that arrives while
+together: shots of one mesh at the same step mode share each kernel launch
+(dgrtm_step_shots).  Each mesh has its own stream, so shots on different meshes overlap on
+the device.  A request that arrives while
 others run joins at the next tick, at a global-step boundary.
 
 The baseline it is compared with is the plain one-shot-at-a-time FP32 solve: requests are
@@ -64,7 +65,7 @@ class MeshSlotPool:
         self.mesh.set_model(rho, c, n_levels).bind("cuda", stream=self.stream)
         self.box = mm.box
         self.n_rec = n_rec
-        self.running: list[tuple[Request, dgrtm.Shot]] = []
+        self.running: list[tuple[Request, dgrtm.Shot, int]] = []    # request, shot, footprint
 
     def spec(self, req: Request) -> dgrtm.ShotSpec:
         sh = I.rtm_shot(box=self.box, src_xy=req.src_xy, f_peak=req.f_peak, n_rec=self.n_rec, t_final=req.t_final)
@@ -135,7 +136,8 @@ def serve_batched(pools: dict, requests: list[Request], hbm_budget: int, max_slo
                   steps_per_tick: int = 16, results: dict | None = None, clock=time.perf_counter,
                   sleep=time.sleep, log=None) -> ServeResult:
     """Continuous batching: admit as slots/memory free up; advance every running shot each tick.
-    `max_slots`: shots running at once on one mesh (an int, or a dict mesh -> int).
+    `max_slots`: shots running at once on one mesh (an int, or a dict mesh -> int; a mesh
+    missing from the dict runs one shot at a time).
     `log(msg)`, if given, is called when a request completes."""
     pending = sorted(requests, key=lambda r: r.arrival)
     waiting: list[Request] = []

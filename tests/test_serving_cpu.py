@@ -90,3 +90,20 @@ def test_batching_beats_sequential_on_fake_costs():
     rb = serve_batched({"m": FakePool(c1)}, reqs1, hbm_budget=10 ** 9, steps_per_tick=4, clock=c1, sleep=c1.sleep)
     rs = serve_sequential({"m": FakePool(c2)}, reqs2, clock=c2, sleep=c2.sleep)
     assert rb.makespan < rs.makespan / 4
+
+
+def test_per_mesh_slot_limits():
+    """A dict of slot limits: one shot at a time on the expensive mesh, several on the cheap one;
+    a mesh missing from the dict runs one shot at a time."""
+    clk = FakeClock()
+    big, small, other = FakePool(clk, total_steps=40), FakePool(clk, total_steps=8), FakePool(clk, total_steps=8)
+    reqs = [Request(i, ("big", "small", "other")[i % 3], (1, 1), 15.0, arrival=0.0, t_final=1.0)
+            for i in range(12)]
+    serve_batched({"big": big, "small": small, "other": other}, reqs, hbm_budget=10 ** 9,
+                  max_slots={"big": 1, "small": 4}, steps_per_tick=4, clock=clk, sleep=clk.sleep)
+    assert all(r.done > r.arrival for r in reqs)
+    assert max(big.launch_sizes) == 1 and max(other.launch_sizes) == 1
+    assert max(small.launch_sizes) == 4
+    # shots on one mesh finish in arrival order when they run one at a time
+    done_big = [r.done for r in reqs if r.mesh == "big"]
+    assert done_big == sorted(done_big)
