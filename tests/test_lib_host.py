@@ -124,3 +124,17 @@ def test_shot_args_struct_matches_c_layout():
     a.struct_size += 8
     a.precision = 7
     assert dgrtm._lib.dgrtm_shot_steps(lm.h, C.byref(a), C.byref(ng), C.byref(nl)) != 0
+
+
+def test_bad_face_types_are_reported():
+    from paper_1506_00907_amd import dgrtm
+    m = I.unit_cube_mesh(2)
+    bc = np.full((m.K, 4), dgrtm.BC_RIGID, dtype=np.int8)
+    bc[:6, :] = 0                                  # not a boundary type (the first cube's boundary faces)
+    with pytest.raises(dgrtm.DgrtmError, match="valid boundary type"):
+        dgrtm.Mesh(3, m.verts, m.etov, face_bc=bc)
+    bc[:6, :] = 4
+    with pytest.raises(dgrtm.DgrtmError, match="valid boundary type"):
+        dgrtm.Mesh(3, m.verts, m.etov, face_bc=bc)
+    bc[:6, :] = dgrtm.BC_FREE
+    dgrtm.Mesh(3, m.verts, m.etov, face_bc=bc)
