@@ -215,8 +215,9 @@ def traffic_from_pmc(workload: str, fetch_dir: str, write_dir: str, copy_fetch_d
             n = r["Kernel_Name"]
             if "step_kernel" not in n:
                 continue
+            # template arguments: step_kernel_dma<N, MODE, PREC>, step_kernel_lowreg<N, MODE, OPS_LDS, PREC>
             targs = [t.strip() for t in n.split("<")[1].split(">")[0].split(",")]
-            if "step_kernel_dma" in n and len(targs) > 2 and targs[2] != "0":
+            if targs[-1] not in ("0", "false"):
                 continue   # the split-BF16 form's launches (same bytes; the roofline line is FP32)
             mode = int(targs[1])
             per.setdefault(names.get(mode, str(mode)), {"fetch": [], "write": []})[key].append(

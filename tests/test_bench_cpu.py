@@ -47,10 +47,14 @@ def test_traffic_from_pmc(tmp_path):
     fp32 = "void dgrtm::step_kernel_dma<4, 0, 0>(dgrtm::StepArgs)"
     bf16 = "void dgrtm::step_kernel_dma<4, 0, 1>(dgrtm::StepArgs)"
     img = "void dgrtm::step_kernel_dma<4, 2, 0>(dgrtm::StepArgs)"
+    # the N >= 5 kernel: <N, MODE, OPS_LDS, PREC>
+    lr32 = "void dgrtm::step_kernel_lowreg<5, 1, true, 0>(dgrtm::StepArgs)"
+    lr16 = "void dgrtm::step_kernel_lowreg<5, 1, true, 1>(dgrtm::StepArgs)"
     _counters(f"{d}/sf", [(fp32, "FETCH_SIZE", 100.0), (fp32, "FETCH_SIZE", 300.0), (bf16, "FETCH_SIZE", 9999.0),
-                          (img, "FETCH_SIZE", 50.0), ("dgrtm::record_kernel", "FETCH_SIZE", 7.0)])
+                          (img, "FETCH_SIZE", 50.0), ("dgrtm::record_kernel", "FETCH_SIZE", 7.0),
+                          (lr32, "FETCH_SIZE", 70.0), (lr16, "FETCH_SIZE", 9999.0)])
     _counters(f"{d}/sw", [(fp32, "WRITE_SIZE", 10.0), (fp32, "WRITE_SIZE", 30.0), (bf16, "WRITE_SIZE", 9999.0),
-                          (img, "WRITE_SIZE", 5.0)])
+                          (img, "WRITE_SIZE", 5.0), (lr32, "WRITE_SIZE", 7.0), (lr16, "WRITE_SIZE", 9999.0)])
     out = bench.traffic_from_pmc("toy", f"{d}/sf", f"{d}/sw", f"{d}/cf", f"{d}/cw", "cmd", profiles_dir=d)
     t = json.load(open(out))
     assert t["copy_calibration"]["fetch_scale"] == pytest.approx(2.0)
@@ -60,6 +64,8 @@ def test_traffic_from_pmc(tmp_path):
     assert fwd["fetch_bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2)
     assert fwd["write_bytes_per_launch"] == pytest.approx(20.0 * 1024)
     assert t["modes"]["image_step"]["bytes_per_launch"] == pytest.approx((50.0 * 2 + 5.0) * 1024)
+    assert t["modes"]["recompute_step"]["launches"] == 1
+    assert t["modes"]["recompute_step"]["bytes_per_launch"] == pytest.approx((70.0 * 2 + 7.0) * 1024)
     assert bench.load_traffic("toy", "forward_step", profiles_dir=d) == pytest.approx((400 + 20) * 1024, abs=0.1)
     # taken on another kernel source: no traffic figure
     t["kernel_source_sha256_16"] = "0" * 16
