@@ -225,3 +225,23 @@ def test_mrab_agrees_with_single_rate_to_third_order():
         qs, _ = T.ab3(op, np.zeros_like(st.q), d, 32 * refine, src=src_sr)
         diffs.append(np.sqrt(op.energy(st.q - qs) / op.energy(qs)))
     assert diffs[0] / diffs[1] > 6.0, diffs
+
+
+def test_neighbourhood_operator_gives_the_whole_mesh_rhs():
+    """The sub-mesh oracle used for sampled checks on meshes too large to set up whole: at the
+    sampled elements it reproduces the whole mesh's rhs (heterogeneous medium, mixed boundaries,
+    both time directions)."""
+    from tests.oracle_cases import neighbourhood_operator
+    m, rho, c, N = I.config_mesh("two_layer_small:6:6:4:3")
+    rng = np.random.default_rng(4)
+    rho = rho * rng.uniform(0.8, 1.5, m.K)
+    bc = rng.choice([BC_RIGID, BC_TRANSPARENT, BC_FREE], size=(m.K, 4))
+    full = Operator(OMesh(get_ref(N), m.verts, m.etov, face_bc=bc), rho, c)
+    el = np.sort(rng.choice(m.K, 60, replace=False))
+    op, sub, loc = neighbourhood_operator(N, m.verts, m.etov, rho, c, el, face_bc=bc)
+    assert sub.size < m.K and np.all(sub[loc] == el)
+    q = rng.standard_normal((m.K, 4, full.ref.Np))
+    for tau_sign in (1.0, -1.0):
+        a = full.rhs(q, tau_sign=tau_sign, elems=el)
+        b = op.rhs(q[sub], tau_sign=tau_sign, elems=loc)
+        assert np.allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
