@@ -9,8 +9,9 @@ run the benchmark's mesh:
   against the same shot with every wavefront on fixed tiles: bit for bit;
 - two shots sharing every launch (two slots, two counters) against each shot alone: bit for bit;
 - the same fixed-tile comparison for the N >= 5 kernel on an 80k-element N = 5 mesh;
-- the rhs on the 4.1M-element, 4-level mesh of the largest shot against the oracle on sampled
-  elements (the oracle set up on the sampled elements and their face neighbours only).
+- the rhs on the 4.1M-element, 4-level mesh of the largest shot, the 786k-element N = 5 serving
+  mesh and the 200k-element mesh at N = 6 against the oracle on sampled elements (the oracle set
+  up on the sampled elements and their face neighbours only).
 """
 import numpy as np
 import pytest
@@ -128,22 +129,34 @@ def test_n5_counter_handout_matches_fixed_tiles():
         assert np.array_equal(u, v)
 
 
-@pytest.fixture(scope="module")
-def largest():
+_LARGE = {}
+
+
+def _large(name, levels):
+    """One large bound mesh at a time (kept across the cases that use it) and a seeded state."""
     from paper_1506_00907_amd import dgrtm, inputs as I
-    mm, rho, c, N = I.config_mesh("big_4m")
-    lm = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, 4).bind("cuda")
-    assert lm.K == 4147200 and lm.L == 4
-    print(f"big_4m bound: {lm.K} elements, {lm.L} levels", flush=True)
-    q = torch.randn((lm.K, 4, lm.Np), generator=torch.Generator().manual_seed(7), dtype=torch.float32)
-    return lm, mm, rho, c, N, q
+    if name not in _LARGE:
+        _LARGE.clear()
+        mm, rho, c, N = I.config_mesh(name)
+        lm = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, levels).bind("cuda")
+        assert lm.L == levels
+        print(f"{name} bound: {lm.K} elements, N = {N}, {lm.L} levels", flush=True)
+        q = torch.randn((lm.K, 4, lm.Np), generator=torch.Generator().manual_seed(7), dtype=torch.float32)
+        _LARGE[name] = (lm, mm, rho, c, N, q)
+    return _LARGE[name]
 
 
-@pytest.mark.parametrize("reversed_time,precision", [(False, 0), (True, 0), (False, 1)])
-def test_largest_mesh_rhs_sampled_vs_oracle(largest, reversed_time, precision):
+# the largest shot's 4.1M-element 4-level mesh, the 786k-element N = 5 serving mesh, and the
+# 200k-element mesh at N = 6 (the precision study), each in both forms
+LARGE_CASES = [(name, levels, rev, prec) for name, levels in (("big_4m", 4), ("srv_800k", 3), ("rtm_200k_n6", 3))
+               for rev, prec in ((False, 0), (True, 0), (False, 1))]
+
+
+@pytest.mark.parametrize("name,levels,reversed_time,precision", LARGE_CASES)
+def test_large_mesh_rhs_sampled_vs_oracle(name, levels, reversed_time, precision):
     from paper_1506_00907_amd import dgrtm
     from tests.oracle_cases import neighbourhood_operator
-    lm, mm, rho, c, N, q = largest
+    lm, mm, rho, c, N, q = _large(name, levels)
     rng = np.random.default_rng(31 + precision)
     el = np.sort(rng.choice(lm.K, 2000, replace=False))
     op, sub, loc = neighbourhood_operator(N, mm.verts, mm.etov, rho, c, el)
@@ -152,5 +165,5 @@ def test_largest_mesh_rhs_sampled_vs_oracle(largest, reversed_time, precision):
     qs = q.numpy()[sub].astype(np.float64)
     ref = op.rhs_reversed(qs, elems=loc) if reversed_time else op.rhs(qs, elems=loc)
     err = rel(got, ref)
-    print(f"big_4m rhs, reversed={reversed_time}, precision={precision}: rel L2 {err:.3e}", flush=True)
+    print(f"{name} rhs, reversed={reversed_time}, precision={precision}: rel L2 {err:.3e}", flush=True)
     assert err < (2e-6 if precision == 0 else 1e-4)
