@@ -5,6 +5,7 @@ run the benchmark's mesh:
 
 - the right-hand side against the FP64 oracle on sampled elements (the oracle evaluates them one
   by one from the same state), in FP32 and in split-BF16;
+- a whole checkpointed shot of three global steps against the oracle's shot on the whole mesh;
 - a whole shot (forward, checkpointed recompute, backward with image) with the counter hand-out
   against the same shot with every wavefront on fixed tiles: bit for bit;
 - two shots sharing every launch (two slots, two counters) against each shot alone: bit for bit;
@@ -56,15 +57,24 @@ def _alone(lm, spec):
     return tr.cpu().numpy(), q, img
 
 
-@pytest.mark.parametrize("reversed_time,precision", [(False, 0), (True, 0), (False, 1), (True, 1)])
-def test_full_size_rhs_sampled_vs_oracle(big, reversed_time, precision):
+@pytest.fixture(scope="module")
+def big_oracle(big):
+    """The oracle's operator and LTS levels on the whole mesh."""
     from oracle.dg import Operator
-    from oracle.mesh import BC_TRANSPARENT, OMesh
+    from oracle.mesh import BC_TRANSPARENT, OMesh, local_dt, lts_levels
     from oracle.refelem import get_ref
-    from paper_1506_00907_amd import dgrtm
     lm, mm, rho, c, N = big
     om = OMesh(get_ref(N), mm.verts, mm.etov, bc_default=BC_TRANSPARENT)
     op = Operator(om, rho, c)
+    lev, L, dtl = lts_levels(local_dt(om.verts, om.etov, c, N), om.EToE, 3)
+    return om, op, lev, L, dtl
+
+
+@pytest.mark.parametrize("reversed_time,precision", [(False, 0), (True, 0), (False, 1), (True, 1)])
+def test_full_size_rhs_sampled_vs_oracle(big, big_oracle, reversed_time, precision):
+    from paper_1506_00907_amd import dgrtm
+    lm, mm, rho, c, N = big
+    om, op = big_oracle[:2]
     rng = np.random.default_rng(21)
     x = om.x
     smooth = np.sin(3.0 * x[..., 0]) * np.cos(2.0 * x[..., 1] + x[..., 2])
@@ -77,6 +87,34 @@ def test_full_size_rhs_sampled_vs_oracle(big, reversed_time, precision):
     ref = op.rhs_reversed(q, elems=el) if reversed_time else op.rhs(q, elems=el)
     # one FP32 operator evaluation; split-BF16 products (hi*hi + hi*lo + lo*hi) on a smooth field
     assert rel(got[el], ref) < (2e-6 if precision == 0 else 1e-4)
+
+
+def test_full_size_shot_vs_oracle(big, big_oracle):
+    """A whole checkpointed shot (forward, recompute, backward with the image) on the whole mesh,
+    three global steps, against the oracle's shot: traces, final source field and image."""
+    from oracle.rtm import COND_CHARACTERISTIC
+    from paper_1506_00907_amd import dgrtm
+    from tests.oracle_cases import oracle_shot
+    lm, mm, rho, c, N = big
+    om, op, lev, L, dtl = big_oracle
+    assert L == lm.L and dtl == lm.dt_local
+    ng = 3
+    spec = _spec(mm, (0.7797, 1.0), ng, lm, ckpt_interval=2)
+    # a receiver beside the source, so that the traces and the image are not zero this early
+    spec.rec = np.vstack([spec.rec, spec.src + np.array([0.001, 0.001, -0.002])])
+    sh = dgrtm.Shot(lm, spec)
+    tr = sh.forward()
+    q = sh.get_state(dgrtm.SOURCE_FIELD).cpu().numpy()
+    sh.adjoint(tr, dgrtm.IMAGE_CHARACTERISTIC, (0.0, 0.0, 1.0), 0)
+    img = sh.image().cpu().numpy()
+    osh = oracle_shot(op, lev, L, dtl, ng, spec)
+    tr_ref = osh.forward(condition=COND_CHARACTERISTIC)
+    assert np.abs(tr_ref).max() > 0
+    assert rel(tr.cpu().numpy(), tr_ref) < 1e-5
+    assert rel(q, osh.S_final) < 1e-5
+    img_ref = osh.adjoint(tr.cpu().numpy().astype(np.float64), condition=COND_CHARACTERISTIC, g_image_start=0)
+    assert np.abs(img_ref).max() > 0
+    assert rel(img, img_ref) < 1e-4
 
 
 def test_full_size_counter_handout_matches_fixed_tiles(big):
