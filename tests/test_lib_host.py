@@ -138,3 +138,10 @@ def test_bad_face_types_are_reported():
         dgrtm.Mesh(3, m.verts, m.etov, face_bc=bc)
     bc[:6, :] = dgrtm.BC_FREE
     dgrtm.Mesh(3, m.verts, m.etov, face_bc=bc)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # the binding has no CPU fallback: without the built library, loading it raises
+    from paper_1506_00907_amd import dgrtm
+    with pytest.raises(ImportError, match="not built"):
+        dgrtm.load_library(str(tmp_path / "libdgrtm.so"))
