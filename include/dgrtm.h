@@ -23,8 +23,12 @@
  *   - Device memory is never allocated by the library: every handle that owns device state
  *     works inside a caller-provided device workspace of the size the matching *_bytes query
  *     returns.  The caller keeps that workspace alive until the handle is destroyed.
- *   - Work is enqueued asynchronously on the HIP stream given at dgrtm_mesh_bind; calls that
- *     return host values synchronise that stream.  Handles are not thread-safe.
+ *   - Work is enqueued asynchronously on the HIP stream given at dgrtm_mesh_bind.  The time
+ *     loop never waits on the host: dgrtm_forward, dgrtm_adjoint, dgrtm_shot_begin,
+ *     dgrtm_step_shots, dgrtm_shot_traces and dgrtm_image return once their work is queued.
+ *     Calls that copy host arrays to the device (dgrtm_mesh_bind, dgrtm_shot_create), return
+ *     host values computed on the device (dgrtm_residual, dgrtm_profile_read) or are test
+ *     hooks synchronise that stream.  Handles are not thread-safe.
  *   - Element numbering in every array is the caller's ("user order"); the library reorders
  *     elements internally (finest time level first).
  *   - Units are any consistent set (the tests use km, s, km/s, g/cm^3).
@@ -103,18 +107,24 @@ dgrtm_status dgrtm_mesh_create(int N, int64_t n_vert, const double *vert_xyz, in
 dgrtm_status dgrtm_set_model(dgrtm_mesh mesh, const double *rho, const double *c, int n_levels_max,
                              double cfl, double *dt_local_out, int *n_levels_out);
 
-/* Device bytes dgrtm_mesh_bind needs (operators, geometry, connectivity). */
+/* Device bytes dgrtm_mesh_bind needs: the reference operators (nodal-DG section, appendix),
+ * the geometric factors and face connectivity of every element (the per-element and per-face
+ * data structures of the implementation section's table), padded per multi-rate level.
+ * Host only.  Errors: DGRTM_ERR_ARG (null mesh, or no dgrtm_set_model yet). */
 dgrtm_status dgrtm_mesh_bytes(dgrtm_mesh mesh, size_t *bytes);
 
 /*
- * Upload the mesh into the device workspace dev_ws (>= dgrtm_mesh_bytes, 256-byte aligned)
+ * Upload the mesh (the data counted by dgrtm_mesh_bytes: implementation section, data-structure
+ * table) into the device workspace dev_ws (>= dgrtm_mesh_bytes, 256-byte aligned)
  * and bind the handle to hip_stream (a hipStream_t; NULL = default stream).
  * Errors: DGRTM_ERR_ARG, DGRTM_ERR_WORKSPACE, DGRTM_ERR_HIP.
  */
 dgrtm_status dgrtm_mesh_bind(dgrtm_mesh mesh, void *dev_ws, size_t ws_bytes, void *hip_stream);
 
 /*
- * Export the integer set-up for checking (host arrays, user element order, any may be NULL):
+ * Export the integer set-up for checking (host arrays, user element order, any may be NULL): the
+ * face connectivity and node maps of the nodal-DG section (vmapM/vmapP of the appendix) and the
+ * levels of the time-stepping section.
  *   EToE, EToF  n_elem x 4 neighbour element and face (self on a boundary face)
  *   vmapP       n_elem x 4 x Nfp global node id k*Np+n of the matching node on the other side
  *   level       n_elem multi-rate level (1 = coarsest)
@@ -123,18 +133,37 @@ dgrtm_status dgrtm_mesh_bind(dgrtm_mesh mesh, void *dev_ws, size_t ws_bytes, voi
 dgrtm_status dgrtm_export_setup(dgrtm_mesh mesh, int32_t *EToE, int8_t *EToF, int32_t *vmapP,
                                 int8_t *level, int64_t *sorted_pos);
 
-/* Reference operators in FP64 (host, row-major): Dr, Ds, Dt (Np x Np), LIFT (Np x 4 Nfp),
- * node coordinates rst (Np x 3).  Any pointer may be NULL. */
+/*
+ * Element holding each point (host work only): the lowest-numbered element, in user order, whose
+ * barycentric coordinates of the point are all >= -1e-12, or -1 for a point outside the mesh.
+ * This is the rule dgrtm_shot_create applies to the source and the receivers; the paper leaves
+ * open which element takes a point on a face or vertex shared by several (point source of the
+ * nodal-DG section, eq. sourceTerm; receivers of the validation section).
+ *   xyz   host, n x 3 doubles;  elem  host, n int64 (user element order)
+ * Errors: DGRTM_ERR_ARG.
+ */
+dgrtm_status dgrtm_locate(dgrtm_mesh mesh, int64_t n, const double *xyz, int64_t *elem);
+
+/* Reference operators in FP64 (host, row-major): the differentiation matrices Dr, Ds, Dt
+ * (Np x Np) and the lift matrix LIFT (Np x 4 Nfp) of the appendix, and the warp-and-blend node
+ * coordinates rst (Np x 3) of the nodal-DG section.  Any pointer may be NULL.
+ * Host only.  Errors: DGRTM_ERR_ARG (null mesh). */
 dgrtm_status dgrtm_export_operators(dgrtm_mesh mesh, double *Dr, double *Ds, double *Dt, double *LIFT,
                                     double *rst);
 
-/* Sizes: Np, Nfp, L, number of global steps and local steps per global step are queried per shot. */
+/* Sizes of the discretisation: order N, nodes per element Np = (N+1)(N+2)(N+3)/6 and per face
+ * Nfp = (N+1)(N+2)/2 (nodal-DG section), elements, number of multi-rate levels L and the finest
+ * step dt_local (time-stepping section).  Any pointer may be NULL.  Host only.
+ * Errors: DGRTM_ERR_ARG (null mesh). */
 dgrtm_status dgrtm_mesh_info(dgrtm_mesh mesh, int *N, int *Np, int *Nfp, int64_t *n_elem, int *n_levels,
                              double *dt_local);
 
+/* Release the host handle (the caller frees the device workspace afterwards).  NULL is ignored. */
 void dgrtm_mesh_destroy(dgrtm_mesh mesh);
 
-/* One RTM shot (versioned plain struct: set struct_size = sizeof(dgrtm_shot_args)). */
+/* One RTM shot (versioned plain struct: set struct_size = sizeof(dgrtm_shot_args)): the point
+ * source and the receiver positions of the RTM procedure (model section), the Ricker wavelet of
+ * the validation and RTM sections, the final time and the storage and precision choices. */
 typedef struct dgrtm_shot_args {
   int32_t struct_size;
   int32_t has_source;      /* 0: no source term (test runs) */
@@ -150,11 +179,16 @@ typedef struct dgrtm_shot_args {
   int32_t reserved;
 } dgrtm_shot_args;
 
-/* Number of global steps of a shot and local steps per global step. */
+/* Number of global steps of a shot (t_final / dt_global rounded up) and local steps per global
+ * step, 2^(L-1) (time-stepping section, Alg. 1).  Host only.  Errors: DGRTM_ERR_ARG. */
 dgrtm_status dgrtm_shot_steps(dgrtm_mesh mesh, const dgrtm_shot_args *args, int64_t *n_global,
                               int32_t *n_local);
 
-/* Device bytes of a shot: both wavefields, FP64 image, checkpoints, segment buffer, traces. */
+/* Device bytes of a shot: the source and receiver wavefields with their AB3 history (eq.
+ * updateAB) and trace copies (eq. updateABcoarse), the FP64 image (eqs. imageP, imageQ), the
+ * source checkpoints and segment records that replace the paper's stored boundary traces (RTM
+ * procedure, model section), and the receiver traces.  This is the footprint that admission
+ * uses.  Host only.  Errors: DGRTM_ERR_ARG. */
 dgrtm_status dgrtm_shot_bytes(dgrtm_mesh mesh, const dgrtm_shot_args *args, size_t *bytes);
 
 /*
@@ -167,14 +201,21 @@ dgrtm_status dgrtm_shot_create(dgrtm_mesh mesh, const dgrtm_shot_args *args, voi
                                dgrtm_shot *out);
 
 /*
- * Forward source run from rest over [0, t_final] with multi-rate AB3 (Alg. 1), saving the AB3
- * state every ckpt_interval global steps in the workspace.  traces_out (device, may be NULL)
+ * Forward source run from rest over [0, t_final] with multi-rate AB3 (time-stepping section,
+ * eqs. updateAB and updateABcoarse, Alg. 1; first stage of the RTM procedure in the model
+ * section), saving the AB3 state every ckpt_interval global steps in the workspace.  traces_out (device, may be NULL)
  * receives the recorded pressure, n_rec x (n_global + 1) floats, sample g at t = g dt_global.
  */
 dgrtm_status dgrtm_forward(dgrtm_shot shot, float *traces_out);
 
 /*
- * Backward receiver run with the data re-injected and the image accumulated (FP64).
+ * Second stage of the RTM procedure (model section): the receiver wavefield runs backward in
+ * time from rest at t_final, with the recorded data re-injected at the receivers and the
+ * penalty parameter of opposite sign (backward-in-time paragraph of the time-stepping
+ * section), and the imaging condition (eq. imageP or imageQ) is accumulated in FP64 from the
+ * exact time integral of the product of both fields' AB3 dense outputs over each element's own
+ * steps (imaging section, eq. updateABcorr with the weights read as ebar_s and, since the
+ * source field is recomputed forward here, the mixed-direction matrix Cmix).
  *   data        device, n_rec x (n_global + 1) floats (linear in time between samples, 0 after t_final)
  *   condition   DGRTM_IMAGE_PRESSURE or DGRTM_IMAGE_CHARACTERISTIC
  *   up          host, 3 doubles: the "up" unit vector of the characteristic split
@@ -195,7 +236,8 @@ dgrtm_status dgrtm_adjoint(dgrtm_shot shot, const float *data, int condition, co
 #define DGRTM_PHASE_DONE 4
 
 /*
- * Reset a shot to run its whole RTM pipeline through dgrtm_step_shots: the forward run, then the
+ * Reset a shot to run its whole RTM pipeline (model section: forward run, backward run with
+ * imaging; the paper sums the images of independent shots) through dgrtm_step_shots: the forward run, then the
  * adjoint (segment recompute and backward run with imaging) with the given parameters (as for
  * dgrtm_adjoint).  data = NULL uses the shot's own recorded traces as the data.  Enqueues the
  * state reset only.
@@ -205,22 +247,32 @@ dgrtm_status dgrtm_shot_begin(dgrtm_shot shot, const float *data, int condition,
 
 /*
  * Advance each of n shots (all on one mesh and bound to one stream) by n_global global steps of
- * its pipeline; shots that are idle or done are skipped.  Shots that are at the same step mode
+ * its pipeline (each step as in dgrtm_forward / dgrtm_adjoint: Alg. 1 with eqs. updateAB,
+ * updateABcoarse and updateABcorr); shots that are idle or done are skipped.  Shots that are at the same step mode
  * (forward, recompute or backward-with-image) and precision share one kernel launch per local
  * step (up to 8 per launch), each with its own time index, sources and buffers.  Asynchronous.
  */
 dgrtm_status dgrtm_step_shots(dgrtm_shot *shots, int n, int64_t n_global);
 
-/* Copy the shot's recorded traces (n_rec x (n_global + 1) floats) into out (device). */
+/* Copy the shot's recorded pressure at the receivers (RTM procedure, model section; the
+ * validation section's receiver traces), n_rec x (n_global + 1) floats, into out (device).
+ * Asynchronous.  Errors: DGRTM_ERR_ARG, DGRTM_ERR_HIP. */
 dgrtm_status dgrtm_shot_traces(dgrtm_shot shot, float *out);
 
-/* Host-side pipeline state: phase (DGRTM_PHASE_*), global steps done and in total. */
+/* Host-side pipeline state of the RTM procedure (model section): phase (DGRTM_PHASE_*), global
+ * steps done and in total.  Host only.  Errors: DGRTM_ERR_ARG. */
 dgrtm_status dgrtm_shot_state(dgrtm_shot shot, int *phase, int64_t *steps_done, int64_t *steps_total);
 
-/* Copy (accumulate = 0) or add (accumulate = 1) the FP64 image into image_out (device, n_elem x Np). */
+/* The image I(x) of eq. imageP or eq. imageQ (model section) as accumulated by the backward
+ * run: copy (accumulate = 0) or add (accumulate = 1, the stack over shots of the model section)
+ * the FP64 nodal image into image_out (device, n_elem x Np, user element order).  Asynchronous on
+ * the bound stream.  Errors: DGRTM_ERR_ARG, DGRTM_ERR_HIP. */
 dgrtm_status dgrtm_image(dgrtm_shot shot, double *image_out, int accumulate);
 
-/* Sum over all samples of (a - b)^2 in FP64 (device float arrays of n values); result on host. */
+/* Misfit of two receiver trace sets (the relative trace error of the validation section is
+ * its square root over the reference's norm): sum over all samples of (a - b)^2 in FP64, a and b
+ * device float arrays of n values; the result is written to the host double *out, so the call
+ * synchronises the stream.  Errors: DGRTM_ERR_ARG, DGRTM_ERR_HIP. */
 dgrtm_status dgrtm_residual(dgrtm_shot shot, const float *a, const float *b, int64_t n, double *out);
 
 /* ---- test hooks (device arrays in user order: n_elem x 4 fields (p, vx, vy, vz) x Np) ---- */
@@ -233,23 +285,26 @@ dgrtm_status dgrtm_residual(dgrtm_shot shot, const float *a, const float *b, int
  * Host only; applies to later launches.  Errors: DGRTM_ERR_ARG (null mesh, negative cap). */
 dgrtm_status dgrtm_mesh_set_launch_cap(dgrtm_mesh mesh, int64_t max_groups);
 
-/* Right-hand side of the semi-discrete system for the given state (no source), forward time
+/* Right-hand side of the semi-discrete system (eqs. dgLocalSchemeP/U, the appendix) for the
+ * given state (no source), forward time
  * (reversed = 0) or reversed time -L(q; -tau) (reversed = 1).  Uses the shot's source-field buffers. */
 dgrtm_status dgrtm_apply_rhs(dgrtm_shot shot, const float *q, float *rhs, int reversed);
 
-/* Set a wavefield's state at time 0 and its AB3 history r(-dt), r(-2 dt) (either may be NULL = 0). */
+/* Set a wavefield's state at time 0 and its AB3 history r(-dt), r(-2 dt) (either may be NULL = 0):
+ * the initialisation step of Alg. 1. */
 dgrtm_status dgrtm_set_state(dgrtm_shot shot, int which, const float *q, const float *hist1, const float *hist2);
 
-/* Read a wavefield's current state. */
+/* Read a wavefield's current nodal state (p, v of eqs. waveSyst1/2). */
 dgrtm_status dgrtm_get_state(dgrtm_shot shot, int which, float *q);
 
-/* Advance a wavefield by n_global global steps (forward; reversed = 1 uses -L(q; -tau)),
+/* Advance a wavefield by n_global global steps of Alg. 1 (forward; reversed = 1 uses -L(q; -tau),
+ * the backward-in-time paragraph of the time-stepping section),
  * with the shot's source when with_source != 0 and the wavefield is the source field. */
 dgrtm_status dgrtm_run(dgrtm_shot shot, int which, int64_t n_global, int reversed, int with_source);
 
 /* ---- measurement ---- */
 
-/* Time every sample_every-th launch of the fused step kernel with a pair of HIP events on the
+/* Measurement, not part of the method: time every sample_every-th launch of the fused step kernel with a pair of HIP events on the
  * bound stream (0 = off); clears earlier samples.  The events are created on the host by the
  * library and released by dgrtm_shot_destroy. */
 dgrtm_status dgrtm_profile_start(dgrtm_shot shot, int sample_every);
@@ -261,6 +316,7 @@ dgrtm_status dgrtm_profile_start(dgrtm_shot shot, int sample_every);
 dgrtm_status dgrtm_profile_read(dgrtm_shot shot, int mode, double *kernel_ms, int64_t *launches,
                                 int64_t *element_steps);
 
+/* Release the host handle and its timing events (the caller frees the workspace). NULL is ignored. */
 void dgrtm_shot_destroy(dgrtm_shot shot);
 
 #ifdef __cplusplus

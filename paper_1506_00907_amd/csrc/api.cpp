@@ -291,6 +291,13 @@ extern "C" dgrtm_status dgrtm_export_setup(dgrtm_mesh m, int32_t *EToE, int8_t *
   return DGRTM_OK;
 }
 
+extern "C" dgrtm_status dgrtm_locate(dgrtm_mesh m, int64_t n, const double *xyz, int64_t *elem) {
+  if (!m || n < 0 || (n > 0 && (!xyz || !elem))) return fail(DGRTM_ERR_ARG, "dgrtm_locate: bad argument");
+  std::vector<double> rst(3 * (size_t)std::max<int64_t>(n, 1));
+  if (n) locate_points(m->hm, n, xyz, elem, rst.data());
+  return DGRTM_OK;
+}
+
 extern "C" dgrtm_status dgrtm_export_operators(dgrtm_mesh m, double *Dr, double *Ds, double *Dt, double *LIFT,
                                                double *rst) {
   if (!m) return fail(DGRTM_ERR_ARG, "dgrtm_export_operators: bad argument");
@@ -991,7 +998,6 @@ extern "C" dgrtm_status dgrtm_image(dgrtm_shot sh, double *image_out, int accumu
   if (!sh || !image_out) return fail(DGRTM_ERR_ARG, "dgrtm_image: bad argument");
   dgrtm_mesh m = sh->mesh;
   HIPCHK(launch_image_to_user(m->ref.Np, sh->img, image_out, m->s2u, m->hm.Ktot, accumulate, m->stream));
-  HIPCHK(hipStreamSynchronize(m->stream));
   return DGRTM_OK;
 }
 

@@ -33,6 +33,7 @@ _SYMBOLS = {
     "dgrtm_mesh_set_launch_cap": (C.c_int32, [C.c_void_p, C.c_int64]),
     "dgrtm_export_setup": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dgrtm_export_operators": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 5),
+    "dgrtm_locate": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "dgrtm_mesh_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                     C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "dgrtm_mesh_destroy": (None, [C.c_void_p]),
@@ -194,6 +195,13 @@ class Mesh:
         if has_model:
             out["level"], out["sorted_pos"] = level, pos
         return out
+
+    def locate(self, xyz):
+        """Element (user order) holding each point, -1 outside the mesh (host work)."""
+        xyz = np.ascontiguousarray(np.atleast_2d(xyz), dtype=np.float64)
+        elem = np.zeros(xyz.shape[0], np.int64)
+        _check(_lib.dgrtm_locate(self.h, xyz.shape[0], _ptr(xyz), _ptr(elem)), "dgrtm_locate")
+        return elem
 
     def export_operators(self):
         Np, F = self.Np, 4 * self.Nfp
@@ -364,3 +372,4 @@ def step_shots(shots, n_global: int = 1):
         return
     with _ordered(shots[0].mesh):
         _check(_lib.dgrtm_step_shots(arr, len(shots), int(n_global)), "dgrtm_step_shots")
+

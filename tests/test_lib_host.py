@@ -145,3 +145,36 @@ def test_missing_library_fails_loudly(tmp_path):
     from paper_1506_00907_amd import dgrtm
     with pytest.raises(ImportError, match="not built"):
         dgrtm.load_library(str(tmp_path / "libdgrtm.so"))
+
+
+def test_points_on_shared_faces_and_vertices_go_to_the_lowest_element():
+    # A point on a face or vertex shared by several elements belongs to the lowest-numbered of
+    # them (the reading taken where the paper is silent).  The expected owner is found from the
+    # vertex lists alone: the elements that have all of the face's vertices, or the vertex.
+    from oracle import source as OS
+    from paper_1506_00907_amd import dgrtm
+    mm, rho, c, N = I.config_mesh("two_layer_small:4:4:3:2")
+    et = np.asarray(mm.etov)
+    rng = np.random.default_rng(3)
+    pts, want = [], []
+    # interior faces: the centroid of a face shared by two elements
+    faces = {}
+    for k in range(et.shape[0]):
+        for tri in ((0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3)):
+            faces.setdefault(tuple(sorted(et[k, list(tri)])), []).append(k)
+    shared = [(f, ks) for f, ks in faces.items() if len(ks) == 2]
+    for i in rng.choice(len(shared), 40, replace=False):
+        f, ks = shared[i]
+        pts.append(mm.verts[list(f)].mean(axis=0))
+        want.append(min(ks))
+    # vertices, interior and on the boundary
+    for v in rng.choice(mm.verts.shape[0], 40, replace=False):
+        pts.append(mm.verts[v])
+        want.append(int(np.flatnonzero((et == v).any(axis=1)).min()))
+    pts, want = np.array(pts), np.array(want)
+    om = OMesh(get_ref(N), mm.verts, mm.etov)
+    assert np.array_equal(OS.locate(om, pts), want)
+    lm = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT)
+    assert np.array_equal(lm.locate(pts), want)
+    # outside the box: -1
+    assert lm.locate(np.array([[5.0, 5.0, 5.0]]))[0] == -1
