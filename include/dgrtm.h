@@ -275,6 +275,24 @@ dgrtm_status dgrtm_image(dgrtm_shot shot, double *image_out, int accumulate);
  * synchronises the stream.  Errors: DGRTM_ERR_ARG, DGRTM_ERR_HIP. */
 dgrtm_status dgrtm_residual(dgrtm_shot shot, const float *a, const float *b, int64_t n, double *out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): dgrtm_residual without a shot.  It computes the same
+ * FP64 sum over all samples of (a - b)^2, allocates nothing, and keeps its partial sums in a
+ * static device array of the library (512 KiB per device, held until the process ends).
+ *   a, b        device float arrays of n values, 0 <= n <= 2^30 (larger n: DGRTM_ERR_ARG, nothing
+ *               launched)
+ *   out         device, one double: receives the sum (0 for n = 0)
+ *   hip_stream  the hipStream_t the two kernels are queued on (NULL = the current device's
+ *               default stream); the call returns without waiting for them
+ * The sum is taken in a fixed order (chunks of 16384 values, then their sums), so equal inputs
+ * give equal results bit for bit.  All calls on one device share its static array: calls whose
+ * kernels overlap on one device (on different streams, or from different threads) race and
+ * must be serialised by the caller.
+ * Errors: DGRTM_ERR_ARG, DGRTM_ERR_HIP.
+ */
+dgrtm_status dgrtm_residual_noalloc(const float *a, const float *b, int64_t n, double *out, void *hip_stream);
+
 /* ---- test hooks (device arrays in user order: n_elem x 4 fields (p, vx, vy, vz) x Np) ---- */
 
 /* Cap on the work-groups of the mesh's step launches (max_groups > 0), or the default grid

@@ -36,6 +36,7 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
         # the step kernel's tile counter back at once, behind the tile copies issued before it
         ("kernels.hip", ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]),
+        ("noalloc.hip", ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]),
     ]
     procs = []
     objs = []

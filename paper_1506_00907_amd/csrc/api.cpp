@@ -42,6 +42,8 @@ struct Bump {
 };
 }  // namespace
 
+int32_t dgrtm::report_error(int32_t code, const std::string &msg) { return fail(code, msg); }
+
 struct dgrtm_mesh_s {
   RefOps ref;
   HostMesh hm;

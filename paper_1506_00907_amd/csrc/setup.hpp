@@ -78,4 +78,7 @@ void mesh_vmapP(const HostMesh &m, const RefOps &ref, int32_t *vmapP);
 // point location: lowest element whose barycentric coordinates are all >= -1e-12; -1 if none
 void locate_points(const HostMesh &m, int64_t n, const double *xyz, int64_t *elem, double *rst);
 
+// record msg as this thread's last error (dgrtm_last_error) and return code
+int32_t report_error(int32_t code, const std::string &msg);
+
 }  // namespace dgrtm

@@ -44,6 +44,7 @@ _SYMBOLS = {
     "dgrtm_adjoint": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
     "dgrtm_image": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int]),
     "dgrtm_residual": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_double)]),
+    "dgrtm_residual_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "dgrtm_apply_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "dgrtm_set_state": (C.c_int32, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dgrtm_get_state": (C.c_int32, [C.c_void_p, C.c_int, C.c_void_p]),
@@ -373,3 +374,20 @@ def step_shots(shots, n_global: int = 1):
     with _ordered(shots[0].mesh):
         _check(_lib.dgrtm_step_shots(arr, len(shots), int(n_global)), "dgrtm_step_shots")
 
+
+def residual_noalloc(a, b, out=None, stream=None):
+    """FP64 sum of (a - b)^2 over two device float tensors, computed by the library without any
+    device allocation of its own (its partial sums live in a static device array).  The result
+    is written into `out` (a device float64 tensor of one element, allocated here if not given)
+    on `stream` (default: the current stream of a's device); the call does not wait for it."""
+    torch = _torch()
+    if a.dtype != torch.float32 or b.dtype != torch.float32 or a.numel() != b.numel():
+        raise DgrtmError("residual_noalloc: a and b must be float32 tensors of equal size")
+    if not (a.is_contiguous() and b.is_contiguous()):
+        raise DgrtmError("residual_noalloc: a and b must be contiguous")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=a.device)
+    st = stream if stream is not None else torch.cuda.current_stream(a.device)
+    _check(_lib.dgrtm_residual_noalloc(a.data_ptr(), b.data_ptr(), a.numel(), out.data_ptr(),
+                                       C.c_void_p(st.cuda_stream)), "dgrtm_residual_noalloc")
+    return out
