@@ -205,3 +205,66 @@ def test_large_mesh_rhs_sampled_vs_oracle(name, levels, reversed_time, precision
     err = rel(got, ref)
     print(f"{name} rhs, reversed={reversed_time}, precision={precision}: rel L2 {err:.3e}", flush=True)
     assert err < (2e-6 if precision == 0 else 1e-4)
+
+
+def _progress(msg):
+    # long oracle runs report their steps on the real stderr (pytest captures sys.stderr)
+    import sys
+    print(f"[fullsize] {msg}", file=sys.__stderr__, flush=True)
+
+
+def _whole_shot_both_forms(name, levels, ng, ckpt):
+    """A whole checkpointed shot (forward, recompute, backward with the characteristic image) on
+    the whole mesh, in FP32 and in split-BF16, against one oracle shot.  Both forms and the
+    oracle's backward run take the oracle's own traces (rounded to FP32) as the data, so the
+    oracle runs once."""
+    from oracle.dg import Operator
+    from oracle.mesh import BC_TRANSPARENT, OMesh, local_dt, lts_levels
+    from oracle.refelem import get_ref
+    from oracle.rtm import COND_CHARACTERISTIC
+    from paper_1506_00907_amd import dgrtm, inputs as I
+    from tests.oracle_cases import oracle_shot
+    mm, rho, c, N = I.config_mesh(name)
+    lm = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, levels).bind("cuda")
+    assert lm.K // 16 >= 3 * 4 * 256    # the full-prefix launches hand tiles out from the counter
+    _progress(f"{name}: oracle set-up ({lm.K} elements, N = {N})")
+    om = OMesh(get_ref(N), mm.verts, mm.etov, bc_default=BC_TRANSPARENT)
+    op = Operator(om, rho, c)
+    lev, L, dtl = lts_levels(local_dt(om.verts, om.etov, c, N), om.EToE, levels)
+    assert L == lm.L and dtl == lm.dt_local
+    spec = _spec(mm, (0.7797, 1.0), ng, lm, ckpt_interval=ckpt)
+    spec.rec = np.vstack([spec.rec, spec.src + np.array([0.001, 0.001, -0.002])])
+    osh = oracle_shot(op, lev, L, dtl, ng, spec)
+    _progress(f"{name}: oracle forward")
+    tr_ref = osh.forward(condition=COND_CHARACTERISTIC)
+    data = tr_ref.astype(np.float32)
+    _progress(f"{name}: oracle backward with image")
+    img_ref = osh.adjoint(data.astype(np.float64), condition=COND_CHARACTERISTIC, g_image_start=0)
+    assert np.abs(tr_ref).max() > 0 and np.abs(img_ref).max() > 0
+    out = {}
+    for prec, tol in ((dgrtm.FP32, 1e-5), (dgrtm.SPLIT_BF16, 1e-4)):
+        spec.precision = prec
+        sh = dgrtm.Shot(lm, spec)
+        tr = sh.forward().cpu().numpy()
+        q = sh.get_state(dgrtm.SOURCE_FIELD).cpu().numpy()
+        sh.adjoint(torch.from_numpy(data).cuda(), dgrtm.IMAGE_CHARACTERISTIC, (0.0, 0.0, 1.0), 0)
+        img = sh.image().cpu().numpy()
+        out[prec] = (rel(tr, tr_ref), rel(q, osh.S_final), rel(img, img_ref))
+        _progress(f"{name} precision {prec}: traces {out[prec][0]:.2e}, source field {out[prec][1]:.2e}, "
+                  f"image {out[prec][2]:.2e}")
+        assert out[prec][0] < tol and out[prec][1] < tol
+        assert out[prec][2] < 1e-4
+        del sh
+    return out
+
+
+def test_n5_whole_shot_vs_oracle():
+    """The N >= 5 kernel (N = 5: operators in LDS) with counter hand-out, every step mode, both
+    forms, against the oracle on an 80k-element mesh."""
+    _whole_shot_both_forms("two_layer_small:28:28:17:5", 3, 3, 2)
+
+
+def test_n6_whole_shot_vs_oracle():
+    """The N = 6 kernel (operators through the caches), both forms, on the 201 600-element mesh of
+    the precision study, against the oracle on the whole mesh."""
+    _whole_shot_both_forms("rtm_200k_n6", 3, 2, 1)
