@@ -7,9 +7,20 @@ with the recorded traces re-injected, characteristic imaging condition accumulat
 then the image export.  Inputs (mesh, model, shot geometry) are seeded synthetic stand-ins
 for the paper's workloads and are resident in HBM before the timed region starts.
 
-Workload "rtm_200k": 2 x 2 x 1 km box, dipping two-layer model 1.5 / 3.0 km/s, 201 600
-jittered tetrahedra refined 2x at the interface, N = 4, 3 levels, 15 Hz Ricker source 8 m
-deep, 100 x 100 receivers 10 m deep, transparent boundaries, t_final = 1 s.
+Workload "big_4m" (the default: the largest shot that fits one GPU): 10 x 10 x 4 km box,
+4 147 200 jittered tetrahedra, the top 0.5 km refined 4x, N = 4, smooth random velocity
+1.5-4.5 km/s (seeded Gaussian-filtered noise) with a 4.5 km/s ellipsoidal inclusion, 4 LTS
+levels, 15 Hz Ricker source 8 m deep at the centre, 256 x 256 receivers 10 m deep, transparent
+boundaries, t_final = 0.04 s by default (checkpointing holds the source wavefield in HBM, which
+bounds the simulated time of a shot on this mesh).
+
+Workload "rtm_200k" (also reported, as a secondary block, after the main one): 2 x 2 x 1 km
+box, dipping two-layer model 1.5 / 3.0 km/s, 201 600 jittered tetrahedra refined 2x at the
+interface, N = 4, 3 levels, 100 x 100 receivers, t_final = 1 s for its own run.
+
+After the timed shots: the split-BF16 form against FP32 on a shorter shot of the same mesh, the
+rtm_200k block, a serving section (a seeded Poisson stream over three meshes, continuous
+batching against one shot at a time) and the FP64 oracle timed on the host.
 
 Prints one JSON line (rank 0, N = 1 only).
 """
@@ -68,8 +79,35 @@ def load_traffic(workload: str, mode_name: str, profiles_dir: str = os.path.join
     return None if m is None else round(m["bytes_per_launch"], 1)
 
 
-def cpu_baseline(mesh_in, rho, c, N, n_levels, seconds_target=15.0):
-    """The FP64 oracle's multi-rate forward stepping on the same mesh, a bounded sample of steps."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def column_elements(mesh_in, width_cells: int = 8) -> "np.ndarray":
+    """Elements of a vertical column of width_cells x width_cells cells at the centre of a Kuhn box
+    (all layers, so that every multi-rate level of the mesh is in it); element id = 6 cell + perm,
+    cells x fastest, then y, then z."""
+    import numpy as np
+    nx, ny, nz = mesh_in.meta["nx"], mesh_in.meta["ny"], mesh_in.meta["nz"]
+    i0, j0 = (nx - width_cells) // 2, (ny - width_cells) // 2
+    ii, jj, mm_ = np.meshgrid(np.arange(i0, i0 + width_cells), np.arange(j0, j0 + width_cells), np.arange(nz),
+                              indexing="ij")
+    cells = (ii + nx * (jj + ny * mm_)).ravel()
+    return np.sort((6 * cells[:, None] + np.arange(6)[None]).ravel())
+
+
+def cpu_baseline(mesh_in, rho, c, N, n_levels, seconds_target=15.0, max_elements=40000):
+    """The FP64 oracle's multi-rate forward stepping, timed on a bounded sample of the workload.
+
+    Meshes larger than max_elements are sampled by a vertical column of cells through the whole
+    depth (the oracle's set-up of the whole 4.1M-element mesh alone would take the better part of
+    an hour): the oracle runs on that sub-mesh, with levels assigned on it by the same rule."""
     import numpy as np
 
     from oracle.dg import Operator
@@ -77,9 +115,23 @@ def cpu_baseline(mesh_in, rho, c, N, n_levels, seconds_target=15.0):
     from oracle.refelem import get_ref
     from oracle.timestep import MRAB
 
-    om = OMesh(get_ref(N), mesh_in.verts, mesh_in.etov, bc_default=BC_TRANSPARENT)
-    op = Operator(om, rho, c)
-    lev, L, dtl = lts_levels(local_dt(om.verts, om.etov, c, N), om.EToE, n_levels)
+    verts, etov, rho_s, c_s, what = mesh_in.verts, mesh_in.etov, rho, c, f"the same {mesh_in.K}-element mesh"
+    if mesh_in.K > max_elements:
+        w = 8
+        while True:
+            el = column_elements(mesh_in, w)
+            if el.size <= max_elements or w == 1:
+                break
+            w -= 1
+        used = np.unique(etov[el])
+        remap = np.full(verts.shape[0], -1, dtype=np.int64)
+        remap[used] = np.arange(used.size)
+        verts, etov, rho_s, c_s = verts[used], remap[etov[el]], rho[el], c[el]
+        what = (f"a {w} x {w}-cell column through the whole depth of the {mesh_in.K}-element mesh "
+                f"({el.size} elements)")
+    om = OMesh(get_ref(N), verts, etov, bc_default=BC_TRANSPARENT)
+    op = Operator(om, rho_s, c_s)
+    lev, L, dtl = lts_levels(local_dt(om.verts, om.etov, c_s, N), om.EToE, n_levels)
     rng = np.random.default_rng(0)
     st = MRAB(op, lev, L, dtl)
     st.set_state(rng.standard_normal((om.K, 4, op.ref.Np)) * 1e-3)
@@ -92,9 +144,10 @@ def cpu_baseline(mesh_in, rho, c, N, n_levels, seconds_target=15.0):
         st.local_step()
     dt = time.perf_counter() - t0
     return {"value": esteps * 4 * op.ref.Np / dt / 1e9, "unit": "GDOF-steps/s", "cores": _threads(),
-            "kind": "oracle",
-            "sample": f"{st.n} local steps ({esteps} element-steps) of the FP64 multi-rate forward run "
-                      f"on the same {om.K}-element mesh, {dt:.1f} s"}
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"{st.n} local steps ({esteps} element-steps, {L} levels "
+                      f"{[int(x) for x in np.bincount(lev, minlength=L + 1)[1:]]}) of the FP64 multi-rate "
+                      f"forward run on {what}, {dt:.1f} s"}
 
 
 def serving_bench(n_requests=12, t_final=0.05, meshes=("srv_50k", "srv_200k", "srv_800k"), seed=7,
@@ -141,10 +194,13 @@ def serving_bench(n_requests=12, t_final=0.05, meshes=("srv_50k", "srv_200k", "s
             "mix_vs_alone_max_rel_image_diff": worst_img, "mix_vs_alone_max_rel_trace_diff": worst_tr}
 
 
-# LTS levels (at most), receiver grid (n x n) and source position of each benchmark shot
+# LTS levels (at most), receiver grid (n x n), source position, default simulated time and
+# default simulated time of the split-BF16 comparison shot of each benchmark shot
 SHOT_SHAPES = {
-    "default": {"levels": 3, "n_rec": 100},                               # the 200k-tet two-layer shot
-    "big_4m": {"levels": 4, "n_rec": 256, "src_xy": (5.0, 5.0)},         # the ~4M-tet 10 x 10 x 4 km shot
+    # the 200k-tet two-layer shot
+    "default": {"levels": 3, "n_rec": 100, "t_final": 1.0, "bf16_t_final": 0.25},
+    # the ~4M-tet 10 x 10 x 4 km shot: 190 global steps; its checkpointed workspace is ~170 GB
+    "big_4m": {"levels": 4, "n_rec": 256, "src_xy": (5.0, 5.0), "t_final": 0.04, "bf16_t_final": 0.01},
 }
 
 
@@ -236,6 +292,54 @@ def traffic_from_pmc(workload: str, fetch_dir: str, write_dir: str, copy_fetch_d
     return path
 
 
+def kernel_trace_summary(trace_dir: str, levels: int) -> str:
+    """Per-kernel calls and durations from a rocprofv3 --kernel-trace CSV, and the step-kernel
+    launches split by active prefix: launch i of a step kernel (in dispatch order) is local step
+    i mod 2^(levels-1) of its global step, whose active levels are the finest 1 + (trailing zeros
+    of i, at most levels - 1)."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not f:
+        raise FileNotFoundError(f"no kernel_trace.csv under {trace_dir}")
+    rows = []
+    for path in f:
+        rows += list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    per = {}
+    for r in rows:
+        per.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    total = sum(sum(v) for v in per.values())
+    lines = [f"{'kernel':<72} {'calls':>7} {'avg_us':>9} {'total_ms':>9} {'%':>6}"]
+    for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{name[:72]:<72} {len(d):>7} {sum(d) / len(d):>9.2f} {sum(d) * 1e-3:>9.2f} "
+                     f"{100 * sum(d) / total:>6.2f}")
+    nl = 2 ** (levels - 1)
+
+    def active(i):
+        n = i % nl
+        if n == 0:
+            return levels
+        k = 0
+        while n % 2 == 0:
+            n //= 2
+            k += 1
+        return min(levels, k + 1)
+
+    lines.append("")
+    lines.append(f"step kernel launches by active prefix (levels active, finest first; {levels} = every level), "
+                 "mean microseconds:")
+    for name, d in sorted(per.items()):
+        if "step_kernel" not in name:
+            continue
+        by = {}
+        for i, x in enumerate(d):
+            by.setdefault(active(i), []).append(x)
+        parts = " ".join(f"{a}:{sum(v) / len(v):.1f}" for a, v in sorted(by.items()))
+        lines.append(f"  {name.split('(')[0]} mean {sum(d) / len(d):.1f}  {parts}")
+    return "\n".join(lines)
+
+
 def _threads() -> int:
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         if os.environ.get(k):
@@ -248,18 +352,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rtm_200k")
-    ap.add_argument("--t-final", type=float, default=1.0)
+    ap.add_argument("--workload", default="big_4m")
+    ap.add_argument("--t-final", type=float, default=None, help="simulated time of a shot (default per workload)")
     ap.add_argument("--sample-every", type=int, default=7, help="time every n-th step-kernel launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--bf16-t-final", type=float, default=0.25,
-                    help="simulated time of the split-BF16 vs FP32 comparison shot (0 = skip)")
-    ap.add_argument("--serving", type=int, default=0, help="requests in the serving section (0 = skip)")
-    ap.add_argument("--serving-t-final", type=float, default=0.05)
+    ap.add_argument("--bf16-t-final", type=float, default=-1.0,
+                    help="simulated time of the split-BF16 vs FP32 comparison shot (0 = skip, <0 = per workload)")
+    ap.add_argument("--secondary", default="rtm_200k", help="second workload reported after the main one ('' = skip)")
+    ap.add_argument("--secondary-t-final", type=float, default=0.25)
+    ap.add_argument("--serving", type=int, default=64, help="requests in the serving section (0 = skip)")
+    ap.add_argument("--serving-t-final", type=float, default=0.01)
     ap.add_argument("--traffic-from-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/step_kernel_<workload>_traffic.json from rocprofv3 --pmc output and exit")
     ap.add_argument("--pmc-command", default="", help="the profiling command, recorded in the traffic JSON")
+    ap.add_argument("--kernel-trace-summary", metavar="TRACE_DIR",
+                    help="print the per-kernel summary of a rocprofv3 --kernel-trace CSV run and exit")
+    ap.add_argument("--levels", type=int, default=0, help="LTS levels of the traced workload (with --kernel-trace-summary)")
     args = ap.parse_args()
+    if args.kernel_trace_summary:
+        lv = args.levels or SHOT_SHAPES.get(args.workload, SHOT_SHAPES["default"])["levels"]
+        print(kernel_trace_summary(args.kernel_trace_summary, lv))
+        return
     if args.traffic_from_pmc:
         print(traffic_from_pmc(args.workload, *args.traffic_from_pmc, command=args.pmc_command))
         return
@@ -273,15 +386,50 @@ def main():
 
     from paper_1506_00907_amd import dgrtm, inputs as I
 
-    log(f"building the {args.workload} mesh ...")
+    out, ctx = run_workload(dgrtm, I, args.workload, args.t_final, args.steps, args.warmup, args.sample_every)
+    mesh, mm, rho, c, N, shape, esteps_global, dof = ctx
+    if args.bf16_t_final != 0:
+        bt = shape["bf16_t_final"] if args.bf16_t_final < 0 else args.bf16_t_final
+        log(f"split-BF16 vs FP32 comparison shots (t_f = {bt} s) ...")
+        out["split_bf16"] = precision_compare(dgrtm, I, mesh, mm.box, shape.get("src_xy", (0.7797, 1.0)),
+                                              shape["n_rec"], bt, esteps_global, dof)
+    del mesh, ctx
+    torch.cuda.empty_cache()
+    if args.secondary and args.secondary != args.workload:
+        log(f"secondary block: {args.secondary} ...")
+        sec, sctx = run_workload(dgrtm, I, args.secondary, args.secondary_t_final, 2, 1, args.sample_every)
+        keep = ("value", "unit", "ms_per_step", "steps", "warmup", "config", "images_per_hour",
+                "single_rate_equivalent_GDOF_steps_s", "roofline")
+        out["secondary"] = {k: sec[k] for k in keep}
+        del sctx
+        torch.cuda.empty_cache()
+    if args.serving > 0:
+        log(f"serving: {args.serving} requests ...")
+        out["serving"] = serving_bench(args.serving, args.serving_t_final)
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline sample ...")
+        out["cpu_baseline"] = cpu_baseline(mm, rho, c, N, shape["levels"])
+    print(json.dumps(out), flush=True)
+
+
+def run_workload(dgrtm, I, workload, t_final, steps, warmup, sample_every):
+    """Set up one workload's mesh and shot, run warmup + timed shots, and return the result
+    dict (metric line fields) and the context the later sections reuse."""
+    import numpy as np
+    import torch
+
+    shape = SHOT_SHAPES.get(workload, SHOT_SHAPES["default"])
+    if t_final is None:
+        t_final = shape["t_final"]
+    log(f"building the {workload} mesh ...")
     ts = time.perf_counter()
-    mm, rho, c, N = I.config_mesh(args.workload)
+    mm, rho, c, N = I.config_mesh(workload)
     log(f"mesh generated: {mm.K} elements in {time.perf_counter() - ts:.1f} s; host set-up and upload ...")
-    shape = SHOT_SHAPES.get(args.workload, SHOT_SHAPES["default"])
     n_levels = shape["levels"]
     mesh = dgrtm.Mesh(N, mm.verts, mm.etov, bc_default=dgrtm.BC_TRANSPARENT).set_model(rho, c, n_levels).bind("cuda")
     src_xy = shape.get("src_xy", (0.7797, 1.0))
-    spec = I.rtm_shot(box=mm.box, src_xy=src_xy, n_rec=shape["n_rec"], t_final=args.t_final)
+    spec = I.rtm_shot(box=mm.box, src_xy=src_xy, n_rec=shape["n_rec"], t_final=t_final)
     shot = dgrtm.Shot(mesh, dgrtm.ShotSpec(t_final=spec.t_final, src=spec.src, f_peak=spec.f_peak,
                                            t_peak=spec.t_peak, rec=spec.rec))
     lev = mesh.export_setup()["level"].astype(np.int64)
@@ -298,19 +446,19 @@ def main():
         shot.adjoint(traces, condition=dgrtm.IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start=0)
         shot.image(img)
 
-    log(f"mesh {args.workload}: {mesh.K} elements, N={N}, {L} levels {list(map(int, hist))}, "
-        f"{ng} global steps per shot")
-    for i in range(args.warmup):
+    log(f"mesh {workload}: {mesh.K} elements, N={N}, {L} levels {list(map(int, hist))}, "
+        f"{ng} global steps per shot, shot workspace {shot.bytes / 1e9:.1f} GB")
+    for i in range(warmup):
         ts = time.perf_counter()
         one_shot()
         torch.cuda.synchronize()
         log(f"warm-up shot {i}: {time.perf_counter() - ts:.2f} s")
     torch.cuda.synchronize()
-    shot.profile_start(args.sample_every)
+    shot.profile_start(sample_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         ts = time.perf_counter()
         one_shot()
         torch.cuda.synchronize()
@@ -321,8 +469,8 @@ def main():
     prof = {m: shot.profile_read(m) for m in (0, 1, 2)}
     # element-steps per shot: forward + recompute + backward, each over every global step
     es_shot = 3 * ng * esteps_global
-    value = es_shot * args.steps * dof / wall / 1e9
-    sr_equiv = 3 * ng * mesh.K * 2 ** (L - 1) * args.steps * dof / wall / 1e9
+    value = es_shot * steps * dof / wall / 1e9
+    sr_equiv = 3 * ng * mesh.K * 2 ** (L - 1) * steps * dof / wall / 1e9
     mode_names = {0: "forward_step", 1: "recompute_step", 2: "image_step"}
     rl = {}
     for m, p in prof.items():
@@ -334,28 +482,29 @@ def main():
                              "kernel_ms_sampled": p["kernel_ms"], "launches_sampled": p["launches"],
                              "algo_bytes_per_launch": b / p["launches"]}
     dom = max(rl, key=lambda k: prof[{v: k2 for k2, v in mode_names.items()}[k]]["kernel_ms"])
-    tr = load_traffic(args.workload, dom)
+    tr = load_traffic(workload, dom)
     out = {
         "metric": "GDOF-steps/s FP32 vs split-BF16 at stated error; shots/h + p50/p99 shot latency",
         "value": round(value, 3),
         "unit": "GDOF-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(1e3 * wall / steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic (seeded mesh, model and shot; no dataset)",
-        "config": {"workload": args.workload, "elements": int(mesh.K), "order_N": int(N), "levels": int(L),
+        "config": {"workload": workload, "elements": int(mesh.K), "order_N": int(N), "levels": int(L),
                    "level_histogram_coarse_to_fine": [int(x) for x in hist], "global_steps": int(ng),
                    "t_final_s": round(ng * mesh.dt_local * 2 ** (L - 1), 6), "receivers": int(shot.n_rec),
                    "image": "characteristic", "parallelism": "single GPU",
                    "shot_workspace_GB": round(shot.bytes / 1e9, 2)},
-        "images_per_hour": round(3600.0 * args.steps / wall, 2),
+        "images_per_hour": round(3600.0 * steps / wall, 2),
         "shot_latency_s": {"p50": round(float(np.percentile(lat, 50)), 3),
-                           "p99": round(float(np.percentile(lat, 99)), 3)},
+                           "p99": round(float(np.percentile(lat, 99)), 3),
+                           "note": "identical shots back to back; the serving section has a request stream"},
         "single_rate_equivalent_GDOF_steps_s": round(sr_equiv, 3),
         "roofline": {"bound": "hbm", "kernel": f"step_kernel ({dom})",
                      "achieved": round(rl[dom]["achieved_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -365,17 +514,7 @@ def main():
     # the timed shot's workspace (checkpoints and segment records) is released before the other
     # sections allocate theirs: on the largest meshes one shot's workspace is most of the HBM
     del shot, traces, img
-    if args.bf16_t_final > 0:
-        log(f"split-BF16 vs FP32 comparison shots (t_f = {args.bf16_t_final} s) ...")
-        out["split_bf16"] = precision_compare(dgrtm, I, mesh, mm.box, src_xy, shape["n_rec"], args.bf16_t_final,
-                                              esteps_global, dof)
-    if args.serving > 0:
-        log(f"serving: {args.serving} requests ...")
-        out["serving"] = serving_bench(args.serving, args.serving_t_final)
-    if not args.no_cpu_baseline:
-        log("oracle CPU baseline sample ...")
-        out["cpu_baseline"] = cpu_baseline(mm, rho, c, N, n_levels)
-    print(json.dumps(out), flush=True)
+    return out, (mesh, mm, rho, c, N, shape, esteps_global, dof)
 
 
 if __name__ == "__main__":

@@ -33,6 +33,8 @@ class Request:
     t_final: float
     admitted: float = -1.0
     done: float = -1.0
+    status: str = "queued"         # queued, done, rejected or failed
+    retries: int = 0
 
     @property
     def latency(self) -> float:
@@ -54,7 +56,13 @@ def make_requests(n: int, rate: float, meshes: list[str], t_final: float, seed: 
 
 
 class MeshSlotPool:
-    """A bound mesh, its stream, and the shots running on it."""
+    """A bound mesh, its stream, and the shots running on it.
+
+    Everything a pool queues runs on its own stream: with that stream current the binding adds no
+    wait against any other stream, so the ticks of different meshes overlap on the device.  The
+    host never waits for a pool inside the serving loop: it records an event after each tick
+    (`mark`), polls events (`ready`), and copies results to pinned host memory asynchronously
+    (`collect_start`)."""
 
     def __init__(self, name: str, n_levels: int = 3, n_rec: int = 100):
         import torch
@@ -65,7 +73,8 @@ class MeshSlotPool:
         self.mesh.set_model(rho, c, n_levels).bind("cuda", stream=self.stream)
         self.box = mm.box
         self.n_rec = n_rec
-        self.running: list[tuple[Request, dgrtm.Shot, int]] = []    # request, shot, footprint
+        self.running: list = []            # Running entries (see serve_batched)
+        self.inflight: list = []           # events of queued ticks, oldest first
 
     def spec(self, req: Request) -> dgrtm.ShotSpec:
         sh = I.rtm_shot(box=self.box, src_xy=req.src_xy, f_peak=req.f_peak, n_rec=self.n_rec, t_final=req.t_final)
@@ -90,11 +99,27 @@ class MeshSlotPool:
         import torch
         with torch.cuda.stream(self.stream):
             shot = dgrtm.Shot(self.mesh, self.spec(req))
-        shot.begin(None, dgrtm.IMAGE_CHARACTERISTIC, (0.0, 0.0, 1.0), 0)
+            shot.begin(None, dgrtm.IMAGE_CHARACTERISTIC, (0.0, 0.0, 1.0), 0)
         return shot
 
     def step(self, shots, n_global: int):
-        dgrtm.step_shots(shots, n_global)
+        import torch
+        with torch.cuda.stream(self.stream):
+            dgrtm.step_shots(shots, n_global)
+
+    def mark(self):
+        import torch
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    @staticmethod
+    def ready(mark) -> bool:
+        return mark.query()
+
+    @staticmethod
+    def wait(mark):
+        mark.synchronize()
 
     def sync(self):
         self.stream.synchronize()
@@ -103,9 +128,28 @@ class MeshSlotPool:
     def is_done(shot) -> bool:
         return shot.state()[0] == dgrtm.PHASE_DONE
 
-    @staticmethod
-    def collect(shot):
-        return shot.traces().cpu().numpy(), shot.image().cpu().numpy()
+    def collect_start(self, shot):
+        """Queue the copies of the shot's traces and image to pinned host memory on the pool's
+        stream; returns (event, result function)."""
+        import torch
+        with torch.cuda.stream(self.stream):
+            tr, img = shot.traces(), shot.image()
+            tr_h = torch.empty(tr.shape, dtype=tr.dtype, pin_memory=True)
+            img_h = torch.empty(img.shape, dtype=img.dtype, pin_memory=True)
+            tr_h.copy_(tr, non_blocking=True)
+            img_h.copy_(img, non_blocking=True)
+            ev = self.mark()
+        held = [tr, img]            # the device copies stay alive until the event has passed
+
+        def result():
+            held.clear()
+            return tr_h.numpy(), img_h.numpy()
+        return ev, result
+
+    def collect(self, shot):
+        ev, result = self.collect_start(shot)
+        ev.synchronize()
+        return result()
 
     def run_alone(self, req: Request):
         import torch
@@ -125,70 +169,156 @@ class ServeResult:
     batched_launch_slots: list = field(default_factory=list)
 
     def summary(self) -> dict:
-        lat = np.array([r.latency for r in self.requests])
-        return {"shots": len(self.requests), "makespan_s": round(self.makespan, 3),
-                "shots_per_hour": round(3600.0 * len(self.requests) / self.makespan, 2),
+        done = [r for r in self.requests if r.status == "done"]
+        lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+        return {"shots": len(done), "makespan_s": round(self.makespan, 3),
+                "shots_per_hour": round(3600.0 * len(done) / max(self.makespan, 1e-9), 2),
                 "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
-                "latency_p99_s": round(float(np.percentile(lat, 99)), 3)}
+                "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+                "rejected": sum(r.status == "rejected" for r in self.requests),
+                "failed": sum(r.status == "failed" for r in self.requests),
+                "retries": sum(r.retries for r in self.requests)}
+
+
+@dataclass
+class Running:
+    req: Request
+    shot: object
+    fp: int
+    finish: object = None          # event after the tick in which the shot's last step was queued
+    collecting: object = None      # (event, result) of the result copies
 
 
 def serve_batched(pools: dict, requests: list[Request], hbm_budget: int, max_slots=8,
                   steps_per_tick: int = 16, results: dict | None = None, clock=time.perf_counter,
-                  sleep=time.sleep, log=None) -> ServeResult:
+                  sleep=time.sleep, log=None, queue_depth: int = 2, max_retries: int = 2) -> ServeResult:
     """Continuous batching: admit as slots/memory free up; advance every running shot each tick.
-    `max_slots`: shots running at once on one mesh (an int, or a dict mesh -> int; a mesh
-    missing from the dict runs one shot at a time).
-    `log(msg)`, if given, is called when a request completes."""
+
+    `max_slots`: shots running at once on one mesh (an int, or a dict mesh -> int; a mesh missing
+    from the dict runs one shot at a time).  Each pool keeps up to `queue_depth` ticks of
+    `steps_per_tick` global steps queued on its stream; a shot retires once the event after its
+    last step has passed and its results have reached the host.
+
+    A request whose footprint exceeds `hbm_budget` is marked "rejected" and the others are
+    served.  When a library call fails (DgrtmError) while admitting or advancing shots, the
+    shots concerned release their slots and memory and their requests go back to the front of
+    the queue, to be run again from the start (a shot's pipeline state after a failed call is
+    not trusted); a request that fails more than `max_retries` times is marked "failed".
+    `log(msg)`, if given, is called when a request completes, is rejected or fails."""
     pending = sorted(requests, key=lambda r: r.arrival)
     waiting: list[Request] = []
     used = 0
     t0 = clock()
-    done_count = 0
+    finished = 0
     ticks = []
-    while done_count < len(requests):
+    order = []                     # (pool, event) of queued ticks, in issue order
+
+    def say(msg):
+        if log is not None:
+            log(msg)
+
+    def release(p, entries, err):
+        """Free the entries' slots and memory; return the requests to run again."""
+        nonlocal used, finished
+        back = []
+        for e in entries:
+            if e in p.running:
+                p.running.remove(e)
+            used -= e.fp
+            e.req.retries += 1
+            if e.req.retries > max_retries:
+                e.req.status = "failed"
+                e.req.done = clock() - t0
+                finished += 1
+                say(f"request {e.req.rid} ({e.req.mesh}) failed: {err}")
+            else:
+                say(f"request {e.req.rid} ({e.req.mesh}) re-queued after: {err}")
+                back.append(e.req)
+        return back
+
+    while finished < len(requests):
         now = clock() - t0
         while pending and pending[0].arrival <= now:
             waiting.append(pending.pop(0))
         # admission in arrival order, by footprint and free slots
-        still = []
+        still, again = [], []
+        progressed = False
         for req in waiting:
             pool = pools[req.mesh]
             fp = pool.footprint(req)
             if fp > hbm_budget:
-                raise ValueError(f"request {req.rid} needs {fp} bytes, more than the budget")
+                req.status = "rejected"
+                req.done = clock() - t0
+                finished += 1
+                progressed = True
+                say(f"request {req.rid} ({req.mesh}) rejected: needs {fp} bytes, the budget is {hbm_budget}")
+                continue
             limit = max_slots.get(req.mesh, 1) if isinstance(max_slots, dict) else max_slots
             if len(pool.running) < limit and used + fp <= hbm_budget:
-                shot = pool.new_shot(req)
                 used += fp
+                progressed = True
+                try:
+                    shot = pool.new_shot(req)
+                except dgrtm.DgrtmError as err:
+                    again += release(pool, [Running(req, None, fp)], err)
+                    continue
                 req.admitted = clock() - t0
-                pool.running.append((req, shot, fp))
+                pool.running.append(Running(req, shot, fp))
             else:
                 still.append(req)
-        waiting = still
-        busy = [p for p in pools.values() if p.running]
-        if not busy:
-            if pending:
-                sleep(max(0.0, min(0.01, pending[0].arrival - now)))
-            continue
-        for p in busy:   # one tick of every mesh: their streams overlap on the device
-            p.step([s for _, s, _ in p.running], steps_per_tick)
-            ticks.append(len(p.running))
-        for p in busy:
-            p.sync()
-            t_now = clock() - t0
-            keep = []
-            for req, shot, fp in p.running:
-                if p.is_done(shot):
-                    req.done = t_now
+        waiting = again + still
+        # queue ticks: every pool keeps up to queue_depth ticks in flight
+        for p in pools.values():
+            while len(p.inflight) < queue_depth:
+                live = [e for e in p.running if e.finish is None]
+                if not live:
+                    break
+                try:
+                    p.step([e.shot for e in live], steps_per_tick)
+                except dgrtm.DgrtmError as err:
+                    waiting[:0] = release(p, live, err)
+                    progressed = True
+                    break
+                ev = p.mark()
+                p.inflight.append(ev)
+                order.append((p, ev))
+                ticks.append(len(live))
+                for e in live:
+                    if p.is_done(e.shot):
+                        e.finish = ev
+                progressed = True
+        # retire: ticks that have passed, then results that have reached the host
+        for p in pools.values():
+            while p.inflight and p.ready(p.inflight[0]):
+                p.inflight.pop(0)
+            for e in list(p.running):
+                if e.finish is not None and e.collecting is None and e.finish not in p.inflight:
+                    e.collecting = p.collect_start(e.shot)
+                    progressed = True
+                if e.collecting is not None and p.ready(e.collecting[0]):
+                    out = e.collecting[1]()
+                    e.req.done = clock() - t0
+                    e.req.status = "done"
                     if results is not None:
-                        results[req.rid] = p.collect(shot)
-                    used -= fp
-                    done_count += 1
-                    if log is not None:
-                        log(f"request {req.rid} ({req.mesh}) done at {t_now:.3f} s")
-                else:
-                    keep.append((req, shot, fp))
-            p.running = keep
+                        results[e.req.rid] = out
+                    p.running.remove(e)
+                    used -= e.fp
+                    finished += 1
+                    progressed = True
+                    say(f"request {e.req.rid} ({e.req.mesh}) done at {e.req.done:.3f} s")
+        order = [(p, ev) for p, ev in order if ev in p.inflight]
+        if progressed:
+            continue
+        # nothing to do until the device or the clock moves on
+        collecting = [(p, e) for p in pools.values() for e in p.running if e.collecting is not None]
+        if order:
+            order[0][0].wait(order[0][1])
+        elif collecting:
+            collecting[0][0].wait(collecting[0][1].collecting[0])
+        elif pending:
+            sleep(max(0.0, min(0.01, pending[0].arrival - (clock() - t0))))
+        elif waiting:
+            raise RuntimeError(f"requests {[r.rid for r in waiting]} can never be admitted (slot limits)")
     return ServeResult(requests, clock() - t0, ticks)
 
 
@@ -204,6 +334,7 @@ def serve_sequential(pools: dict, requests: list[Request], results: dict | None 
         req.admitted = clock() - t0
         out = pool.run_alone(req)
         req.done = clock() - t0
+        req.status = "done"
         if results is not None:
             results[req.rid] = out
         if log is not None:

@@ -71,3 +71,32 @@ def test_traffic_from_pmc(tmp_path):
     t["kernel_source_sha256_16"] = "0" * 16
     json.dump(t, open(out, "w"))
     assert bench.load_traffic("toy", "forward_step", profiles_dir=d) is None
+
+
+def test_column_sample_spans_the_depth():
+    import numpy as np
+    from paper_1506_00907_amd import inputs as I
+    m = I.two_layer_mesh(10, 8, 5, seed=1)
+    el = bench.column_elements(m, 3)
+    assert el.size == 3 * 3 * 5 * 6 and np.all(np.diff(el) > 0)
+    cells = el // 6
+    assert set((cells // (10 * 8)).tolist()) == set(range(5))            # every layer
+    assert set((cells % 10).tolist()) == {3, 4, 5} and set(((cells // 10) % 8).tolist()) == {2, 3, 4}
+
+
+def test_kernel_trace_summary_classifies_launches_by_local_step(tmp_path):
+    # two global steps of a 3-level schedule: local steps 0..3 activate 3, 1, 2, 1 levels
+    d = tmp_path / "trace" / "host" / "1"
+    d.mkdir(parents=True)
+    rows = ["Kind,Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp"]
+    dur = {3: 30000, 1: 10000, 2: 20000}
+    t = 0
+    for i in range(8):
+        a = (3, 1, 2, 1)[i % 4]
+        rows.append(f'KERNEL_DISPATCH,{2 * i + 1},"void dgrtm::step_kernel_dma<4, 0, 0>(dgrtm::StepArgs)",{t},{t + dur[a]}')
+        rows.append(f'KERNEL_DISPATCH,{2 * i + 2},"dgrtm::record_kernel(float const*)",{t},{t + 1000}')
+        t += 100000
+    (d / "run_kernel_trace.csv").write_text("\n".join(rows) + "\n")
+    out = bench.kernel_trace_summary(str(tmp_path / "trace"), 3)
+    assert "mean 17.5  1:10.0 2:20.0 3:30.0" in out
+    assert "dgrtm::record_kernel(float const*)" in out

@@ -48,3 +48,30 @@ def test_outputs_ordered_against_a_busy_mesh_stream():
     assert np.array_equal(got_img, want_img)
     assert np.array_equal(got_tr, want_tr)
     pool.sync()
+
+
+def test_meshes_do_not_wait_for_each_other():
+    """A long tick queued on one pool, then a short tick on another: the short one finishes first.
+    (If a pool's tick waited for the work already queued on another pool's stream, it would end
+    after the long one.)"""
+    from paper_1506_00907_amd import dgrtm, serving as S
+    long_pool = S.MeshSlotPool("two_layer_small:10:10:6:4", n_rec=4)
+    short_pool = S.MeshSlotPool("two_layer_small:3:3:2:2", n_rec=4)
+    req = S.Request(0, long_pool.name, (1.0, 1.0), 15.0, 0.0, 0.2)
+    a = long_pool.new_shot(req)
+    b = short_pool.new_shot(S.Request(1, short_pool.name, (1.0, 1.0), 15.0, 0.0, 0.2))
+    torch.cuda.synchronize()
+    ref = torch.cuda.Event(enable_timing=True)
+    ref.record()
+    torch.cuda.synchronize()
+    ends = []
+    for pool, shot, n in ((long_pool, a, 40), (short_pool, b, 1)):
+        pool.step([shot], n)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(pool.stream)
+        ends.append(e)
+    torch.cuda.synchronize()
+    t_long, t_short = (ref.elapsed_time(e) for e in ends)
+    print(f"long tick ends at {t_long:.3f} ms, short tick at {t_short:.3f} ms", flush=True)
+    assert a.state()[1] == 40 and b.state()[1] == 1
+    assert t_short < 0.5 * t_long
