@@ -22,7 +22,12 @@ Readings where the paper is silent or inconsistent:
   * exterior states at the domain boundary: rigid wall p+ = p-,
     v+ = v- - 2(n.v-)n; free surface p+ = -p-, v+ = v-; transparent q+ = 0;
     on boundary faces tau_p = 1/Z-, tau_v = Z-;
-  * backward-in-time runs use tau -> -tau (strictly negative penalties).
+  * backward-in-time runs use tau -> -tau (strictly negative penalties);
+  * boundary-trace replay (the source field re-simulated backward in time, RTM
+    procedure of the model section): on every boundary face the exterior state
+    is the trace the forward run had there at the same time, p+ = p-_fwd and
+    n.v+ = (n.v-)_fwd, whatever the boundary type; tau keeps its boundary value
+    (the face-symmetric value with equal impedances on both sides).
 """
 from __future__ import annotations
 
@@ -67,12 +72,14 @@ class Operator:
 
     # ------------------------------------------------------------------ rhs
     def rhs(self, q: np.ndarray, qf: np.ndarray | None = None, tau_sign: float = 1.0,
-            elems: np.ndarray | None = None) -> np.ndarray:
+            elems: np.ndarray | None = None, replay: np.ndarray | None = None) -> np.ndarray:
         """Right-hand side of the elements `elems` (all if None).
 
         q: (K,4,Np) nodal fields (p, vx, vy, vz).  qf: (K,4,Nfp,2) trace copies
         used for the surface terms (both sides), as in the surface kernel of the
-        paper; if None the traces of q are used.
+        paper; if None the traces of q are used.  replay: (n,4,Nfp,2) recorded
+        traces (p, n.v with the element's own normal) of the rows `elems`; where
+        given, they are the exterior state on every boundary face.
         """
         m, R = self.m, self.ref
         if qf is None:
@@ -108,6 +115,10 @@ class Operator:
         nvP = np.where(bc == BC_FREE, nvM, nvP)
         pP = np.where(bc == BC_TRANSPARENT, 0.0, pP)
         nvP = np.where(bc == BC_TRANSPARENT, 0.0, nvP)
+        if replay is not None:
+            bd = m.is_bdry[ks][:, :, None]
+            pP = np.where(bd, replay[..., 0], pP)
+            nvP = np.where(bd, replay[..., 1], nvP)
         dp = pP - pM
         dnv = nvP - nvM
         taup = tau_sign * self.tau_p[ks][:, :, None]
@@ -122,9 +133,9 @@ class Operator:
         out[:, 1:4] -= np.einsum("kfd,kfn->kdn", m.n[ks], g)
         return out
 
-    def rhs_reversed(self, q, qf=None, elems=None):
+    def rhs_reversed(self, q, qf=None, elems=None, replay=None):
         """Right-hand side in reversed time s = t_f - t: -L(q; -tau)."""
-        return -self.rhs(q, qf, tau_sign=-1.0, elems=elems)
+        return -self.rhs(q, qf, tau_sign=-1.0, elems=elems, replay=replay)
 
     # ------------------------------------------------------------------ energy
     def energy(self, q: np.ndarray) -> float:

@@ -149,11 +149,14 @@ class MRAB:
     levels: (K,) in 1..L, 1 = coarsest; Delta t_l = 2^(L-l) dt_local; one global step is
     2^(L-1) local steps.  `reversed_time` integrates dq/ds = -L(q; -tau) (backward run).
     `src(r, t_start, elems)` may add source terms into r (rows for `elems`).
-    `on_eval(k_idx, step_idx, q_k, r_k, hist_k)` observes each element-step (for imaging).
+    `on_eval(k_idx, step_idx, q_k, hist_k)` observes each element-step before its update (for
+    imaging); `on_update(k_idx, step_idx)` is called after the update of the elements `k_idx`,
+    step_idx being their new own step.  `replay(elems, n)` returns, for a boundary-trace replay
+    run, the exterior traces (len(elems), 4, Nfp, 2) of the elements evaluated at local step n.
     """
 
     def __init__(self, op: Operator, levels: np.ndarray, L: int, dt_local: float,
-                 reversed_time: bool = False, src=None, on_eval=None):
+                 reversed_time: bool = False, src=None, on_eval=None, on_update=None, replay=None):
         self.op = op
         self.lev = np.asarray(levels, dtype=np.int64)
         self.L = int(L)
@@ -161,6 +164,8 @@ class MRAB:
         self.rev = reversed_time
         self.src = src
         self.on_eval = on_eval
+        self.on_update = on_update
+        self.replay = replay
         self.n = 0
         K = op.m.K
         self.q = np.zeros((K, 4, op.ref.Np))
@@ -169,12 +174,15 @@ class MRAB:
         self.stride = 2 ** (self.L - self.lev)          # local steps per own step
 
     def set_state(self, q, hist2=None):
+        """State at the start and, optionally, the AB3 history hist2 = (r(-dt), r(-2 dt)) of every
+        element at its own step (the first update then uses r(0), r(-dt), r(-2 dt), eq. updateAB)."""
         self.q = np.array(q, dtype=np.float64)
         self.qf = self.op.traces(self.q)
         self.hist[:] = 0.0
         if hist2 is not None:
-            self.hist[:, 1] = hist2[0]
-            self.hist[:, 2] = hist2[1]
+            # local_step shifts the history one slot before it stores the new rhs in slot 0
+            self.hist[:, 0] = hist2[0]
+            self.hist[:, 1] = hist2[1]
 
     @property
     def n_local(self) -> int:
@@ -186,7 +194,9 @@ class MRAB:
         dtl = self.dt_local * self.stride                # (K,) own step
         t_start = n * self.dt_local
         ev = np.nonzero(n % self.stride == 0)[0]          # unknowns evaluated at t_start
-        r = op.rhs_reversed(self.q, self.qf, elems=ev) if self.rev else op.rhs(self.q, self.qf, elems=ev)
+        rp = None if self.replay is None else self.replay(ev, n)
+        r = (op.rhs_reversed(self.q, self.qf, elems=ev, replay=rp) if self.rev
+             else op.rhs(self.q, self.qf, elems=ev, replay=rp))
         if self.src is not None:
             self.src(r, t_start, ev)
         self.hist[ev, 2] = self.hist[ev, 1]
@@ -203,6 +213,8 @@ class MRAB:
             step = dtl[ks][:, None, None]
             self.q[ks] = self.q[ks] + step * (AB_A[0] * h[:, 0] + AB_A[1] * h[:, 1] + AB_A[2] * h[:, 2])
             self.qf[ks] = op.traces(self.q, ks)
+            if self.on_update is not None:
+                self.on_update(ks, (n + 1) // self.stride[ks])
         # coarse neighbours of elements evaluated at t_new get half-step traces
         nb = op.m.EToE
         touched = np.zeros(op.m.K, dtype=bool)

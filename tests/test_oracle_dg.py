@@ -198,6 +198,15 @@ def test_mrab_single_level_is_ab3_bitwise():
         st.global_step()
     q2, _ = T.ab3(op, q0, dtl, 6)
     assert np.array_equal(st.q, q2)
+    # with a given history (r(-dt), r(-2 dt)): the first update uses r(0), r(-dt), r(-2 dt)
+    h = rng.standard_normal((2, op.m.K, 4, op.ref.Np))
+    st = T.MRAB(op, np.ones(op.m.K, dtype=int), 1, dtl)
+    st.set_state(q0, hist2=h)
+    st.global_step()
+    q1, _ = T.ab3(op, q0, dtl, 1, hist=h)
+    r0 = op.rhs(q0)
+    assert np.array_equal(st.q, q1)
+    assert np.allclose(q1, q0 + dtl * (23 / 12 * r0 - 16 / 12 * h[0] + 5 / 12 * h[1]), rtol=0, atol=1e-12)
 
 
 def test_mrab_agrees_with_single_rate_to_third_order():
