@@ -61,6 +61,22 @@ typedef int32_t dgrtm_status;
  * q+- = p +- rho c up.v (eqs. imageQ, charact) */
 #define DGRTM_IMAGE_PRESSURE 0
 #define DGRTM_IMAGE_CHARACTERISTIC 1
+/* or'ed into the condition: each own step's contribution by the trapezoid rule dt/2 (S R at both
+ * ends of the step; eq. trapRule, its sign read as "+") instead of the exact integral of the two
+ * fields' AB3 dense outputs (eq. updateABcorr) */
+#define DGRTM_IMAGE_TRAPEZOID 0x100
+
+/* how the source wavefield is made available to the backward run (dgrtm_shot_args.storage):
+ *   DGRTM_STORE_CHECKPOINTS  the AB3 state every ckpt_interval global steps, the source field
+ *                            recomputed forward segment by segment (memory ~ sqrt(steps))
+ *   DGRTM_STORE_BOUNDARY     the paper's strategy (RTM procedure of the model section; section on
+ *                            memory transfers): p and n.v at the boundary face nodes after every
+ *                            own step, and the final state; the source field is re-simulated
+ *                            backward in time (penalties of opposite sign) with these traces as the
+ *                            exterior state of every boundary face, beside the receiver field
+ *                            (memory ~ steps x boundary faces) */
+#define DGRTM_STORE_CHECKPOINTS 0
+#define DGRTM_STORE_BOUNDARY 1
 
 /* arithmetic of the element operator products: FP32 MFMA, or split-BF16 MFMA (A x evaluated as
  * A_hi x_hi + A_hi x_lo + A_lo x_hi with A = A_hi + A_lo, x = x_hi + x_lo in bf16, FP32 accumulation).
@@ -176,7 +192,7 @@ typedef struct dgrtm_shot_args {
   double t_final;          /* rounded up to a whole number of global steps */
   int64_t ckpt_interval;   /* global steps between source checkpoints; 0 = chosen to minimise memory */
   int32_t precision;       /* DGRTM_FP32 or DGRTM_SPLIT_BF16 */
-  int32_t reserved;
+  int32_t storage;         /* DGRTM_STORE_CHECKPOINTS (ckpt_interval applies) or DGRTM_STORE_BOUNDARY */
 } dgrtm_shot_args;
 
 /* Number of global steps of a shot (t_final / dt_global rounded up) and local steps per global
@@ -186,9 +202,10 @@ dgrtm_status dgrtm_shot_steps(dgrtm_mesh mesh, const dgrtm_shot_args *args, int6
 
 /* Device bytes of a shot: the source and receiver wavefields with their AB3 history (eq.
  * updateAB) and trace copies (eq. updateABcoarse), the FP64 image (eqs. imageP, imageQ), the
- * source checkpoints and segment records that replace the paper's stored boundary traces (RTM
- * procedure, model section), and the receiver traces.  This is the footprint that admission
- * uses.  Host only.  Errors: DGRTM_ERR_ARG. */
+ * receiver traces, and by storage: the source checkpoints and segment records, or the boundary
+ * traces of every own step, two saved states and one global step of segment records (RTM
+ * procedure, model section).  This is the footprint that admission uses.  Host only.
+ * Errors: DGRTM_ERR_ARG. */
 dgrtm_status dgrtm_shot_bytes(dgrtm_mesh mesh, const dgrtm_shot_args *args, size_t *bytes);
 
 /*
@@ -217,11 +234,18 @@ dgrtm_status dgrtm_forward(dgrtm_shot shot, float *traces_out);
  * steps (imaging section, eq. updateABcorr with the weights read as ebar_s and, since the
  * source field is recomputed forward here, the mixed-direction matrix Cmix).
  *   data        device, n_rec x (n_global + 1) floats (linear in time between samples, 0 after t_final)
- *   condition   DGRTM_IMAGE_PRESSURE or DGRTM_IMAGE_CHARACTERISTIC
+ *   condition   DGRTM_IMAGE_PRESSURE or DGRTM_IMAGE_CHARACTERISTIC, optionally | DGRTM_IMAGE_TRAPEZOID
  *   up          host, 3 doubles: the "up" unit vector of the characteristic split
  *   g_image_start  image only over [g_image_start dt_global, t_final]; the backward run stops there
- * The source wavefield is recomputed segment by segment from the checkpoints.  Requires a
- * completed dgrtm_forward.  The image is reset at the start of the call.
+ * With DGRTM_STORE_CHECKPOINTS the source wavefield is recomputed forward segment by segment
+ * from the checkpoints and paired with the receiver field step by step (the weights Cmix of an
+ * integral of one forward and one backward dense output).  With DGRTM_STORE_BOUNDARY it is
+ * re-simulated backward from its final state with the recorded boundary traces, in lockstep with
+ * the receiver field, and the image takes the both-backward form of eq. updateABcorr (ebar_s,
+ * and C as printed); the AB3 history of that backward run at t_final, on which the paper is
+ * silent, is extrapolated (third order) from its reversed-time rhs at the global times t_final,
+ * t_final - dt_global and t_final - 2 dt_global.  Requires a completed dgrtm_forward.  The image
+ * is reset at the start of the call.
  */
 dgrtm_status dgrtm_adjoint(dgrtm_shot shot, const float *data, int condition, const double *up,
                            int64_t g_image_start);

@@ -59,6 +59,10 @@ struct dgrtm_mesh_s {
   uint32_t *tile_ctr = nullptr;  // per shot slot: next-tile and finished-wave counters of the step kernel
   int64_t max_groups = 0;        // cap on step-launch work-groups (0: one per compute unit)
   std::vector<int> h_eflag;  // base flags (valid, has finer neighbour)
+  // boundary faces (for the boundary-trace record): sorted position * 4 + face, finest level first
+  int *bface = nullptr;
+  int64_t n_bfaces = 0;
+  int64_t bnd_cnt[kMaxLevels] = {0}, bnd_begin[kMaxLevels] = {0};
   int64_t n_ops = 0, n_ops_bf16 = 0;
 };
 
@@ -91,6 +95,13 @@ struct dgrtm_shot_s {
   float *wavelet = nullptr;
   float *traces = nullptr;     // n_rec x (n_global + 1)
   double *red = nullptr;       // FP64 reduction scratch
+  // boundary-trace storage (DGRTM_STORE_BOUNDARY): the record, and the states at the starts of
+  // the last two global steps (index 0: global time NG - 1, index 1: NG - 2)
+  bool replay = false;
+  float *bnd_rec = nullptr;
+  int64_t bnd_off[kMaxLevels] = {0};
+  float *qsave[2] = {nullptr, nullptr};
+  bool trapezoid = false;
   bool forward_done = false;
   // pipeline state, advanced one global step at a time (dgrtm_step_shots)
   int ph = DGRTM_PHASE_IDLE;
@@ -165,7 +176,12 @@ static size_t mesh_layout(dgrtm_mesh m, Bump &b) {
   int8_t *nidx = b.take<int8_t>((size_t)4 * 4 * 6 * m->ref.Nfp);
   int64_t *s2u = b.take<int64_t>((size_t)K);
   uint32_t *tctr = b.take<uint32_t>((size_t)2 * kMaxSlots);
+  int64_t nbf = 0;
+  for (int64_t i = 0; i < 4 * h.K; ++i) nbf += h.bc[i] != 0;
+  int *bface = b.take<int>((size_t)std::max<int64_t>(nbf, 1));
   if (b.base) {  // a sizing pass (no base) leaves the handle untouched
+    m->bface = bface;
+    m->n_bfaces = nbf;
     m->geo = geo;
     m->nbr = nbr;
     m->ncode = ncode;
@@ -207,9 +223,15 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
   std::vector<float> geo((size_t)kGeo * K, 0.0f);
   std::vector<int> nbr((size_t)4 * K, -2), ncode((size_t)4 * K, 0);
   m->h_eflag.assign(K, 0);
+  // boundary faces in sorted order (finest level first); a boundary face's code is its index among
+  // its level's boundary faces, a padding element's codes are -1
+  std::vector<int> bface;
+  for (int l = 0; l < kMaxLevels; ++l) m->bnd_cnt[l] = m->bnd_begin[l] = 0;
+  int cur_level = -1;
   for (int64_t s = 0; s < K; ++s) {
     int64_t u = h.sorted_to_user[s];
     if (u < 0) {
+      for (int f = 0; f < 4; ++f) ncode[tix(4, f, s)] = -1;
       geo[tix(kGeo, 0, s)] = geo[tix(kGeo, 4, s)] = geo[tix(kGeo, 8, s)] = 1.0f;
       geo[tix(kGeo, 9, s)] = geo[tix(kGeo, 10, s)] = geo[tix(kGeo, 11, s)] = 1.0f;
       continue;
@@ -228,6 +250,13 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
         taup = 1.0 / Zm;
         tauv = Zm;
         nbr[tix(4, f, s)] = -b_;
+        const int lv = h.level[u];
+        if (lv != cur_level) {
+          cur_level = lv;
+          m->bnd_begin[lv - 1] = (int64_t)bface.size();
+        }
+        ncode[tix(4, f, s)] = (int)m->bnd_cnt[lv - 1]++;
+        bface.push_back((int)(s * 4 + f));
       } else {
         const double Zp = h.rho[u2] * h.c[u2];
         taup = 2.0 / (Zm + Zp);
@@ -264,6 +293,9 @@ extern "C" dgrtm_status dgrtm_mesh_bind(dgrtm_mesh m, void *dev_ws, size_t ws_by
   HIPCHK(hipMemcpyAsync(m->ops_bf16, fragb.data(), fragb.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(m->nbr_index, nidx.data(), nidx.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(m->s2u, h.sorted_to_user.data(), K * 8, hipMemcpyHostToDevice, st));
+  if ((int64_t)bface.size() != m->n_bfaces) return fail(DGRTM_ERR_MESH, "dgrtm_mesh_bind: boundary face count");
+  if (!bface.empty())
+    HIPCHK(hipMemcpyAsync(m->bface, bface.data(), bface.size() * 4, hipMemcpyHostToDevice, st));
   // the step kernel leaves its counters at zero when it ends; they start at zero here
   const std::vector<uint32_t> zero(2 * kMaxSlots, 0u);
   HIPCHK(hipMemcpyAsync(m->tile_ctr, zero.data(), zero.size() * 4, hipMemcpyHostToDevice, st));
@@ -342,6 +374,8 @@ static dgrtm_status check_args(dgrtm_mesh m, const dgrtm_shot_args *a) {
   if (a->n_rec < 0 || (a->n_rec > 0 && !a->rec_xyz)) return fail(DGRTM_ERR_ARG, "bad receivers");
   if (a->ckpt_interval < 0) return fail(DGRTM_ERR_ARG, "bad ckpt_interval");
   if (a->precision != DGRTM_FP32 && a->precision != DGRTM_SPLIT_BF16) return fail(DGRTM_ERR_ARG, "bad precision");
+  if (a->storage != DGRTM_STORE_CHECKPOINTS && a->storage != DGRTM_STORE_BOUNDARY)
+    return fail(DGRTM_ERR_ARG, "bad storage");
   return DGRTM_OK;
 }
 
@@ -363,6 +397,7 @@ extern "C" dgrtm_status dgrtm_shot_steps(dgrtm_mesh m, const dgrtm_shot_args *a,
 }
 
 static int64_t choose_interval(dgrtm_mesh m, const dgrtm_shot_args *a, int64_t ng) {
+  if (a->storage == DGRTM_STORE_BOUNDARY) return 1;   // segment records of one global step at a time
   if (a->ckpt_interval > 0) return std::min(a->ckpt_interval, ng);
   const HostMesh &h = m->hm;
   const int Np = m->ref.Np;
@@ -371,6 +406,14 @@ static int64_t choose_interval(dgrtm_mesh m, const dgrtm_shot_args *a, int64_t n
   for (int l = 1; l <= h.L; ++l) seg += 2.0 * Np * (double)level_size_h(h, l) * (1 << (l - 1));
   int64_t C = (int64_t)std::llround(std::sqrt((double)ng * ck / std::max(seg, 1.0)));
   return std::min<int64_t>(std::max<int64_t>(C, 1), ng);
+}
+
+// boundary faces per level (index l - 1)
+static void boundary_counts(const HostMesh &h, int64_t *cnt) {
+  for (int l = 0; l < kMaxLevels; ++l) cnt[l] = 0;
+  for (int64_t u = 0; u < h.K; ++u)
+    for (int f = 0; f < 4; ++f)
+      if (h.bc[4 * u + f] != 0) ++cnt[h.level[u] - 1];
 }
 
 static size_t shot_layout(dgrtm_shot sh, Bump &b) {
@@ -385,6 +428,18 @@ static size_t shot_layout(dgrtm_shot sh, Bump &b) {
   }
   sh->img = b.take<double>((size_t)Np * K);
   sh->ckpt = b.take<float>((size_t)sh->n_ckpt * 3 * state_row(Np) * K);
+  if (sh->replay) {
+    // level l: rows j = 0 .. NG 2^(l-1) of its boundary faces, 2 FS floats each
+    const int64_t row = 2 * trace_face_stride(m->ref.Nfp);
+    int64_t cnt[kMaxLevels], off = 0;
+    boundary_counts(h, cnt);
+    for (int l = 1; l <= h.L; ++l) {
+      sh->bnd_off[l - 1] = off;
+      off += ((sh->n_global << (l - 1)) + 1) * cnt[l - 1] * row;
+    }
+    sh->bnd_rec = b.take<float>((size_t)std::max<int64_t>(off, 4));
+    for (int i = 0; i < 2; ++i) sh->qsave[i] = b.take<float>((size_t)state_row(Np) * K);
+  }
   int64_t oq = 0, orr = 0;
   for (int l = 1; l <= h.L; ++l) {
     const int64_t P = level_size_h(h, l), nst = sh->C * ((int64_t)1 << (l - 1));
@@ -415,8 +470,9 @@ static dgrtm_shot new_shot(dgrtm_mesh m, const dgrtm_shot_args *a) {
   sh->mesh = m;
   sh->args = *a;
   shot_steps(m, a, sh->n_global, sh->n_local);
+  sh->replay = a->storage == DGRTM_STORE_BOUNDARY;
   sh->C = choose_interval(m, a, sh->n_global);
-  sh->n_ckpt = (sh->n_global + sh->C - 1) / sh->C;
+  sh->n_ckpt = sh->replay ? 0 : (sh->n_global + sh->C - 1) / sh->C;
   sh->src.n = a->has_source ? 1 : 0;
   sh->rec.n = a->n_rec;
   return sh;
@@ -558,6 +614,7 @@ static StepArgs mesh_args(dgrtm_mesh m, int precision, int mode, bool reversed, 
   a.Ktot = h.Ktot;
   a.L = h.L;
   fill_level_begin(h, a.lev_begin);
+  for (int l = 0; l < kMaxLevels; ++l) a.bnd_cnt[l] = m->bnd_cnt[l];
   a.dt_local = h.dt_local;
   a.tau_sign = reversed ? -1.0f : 1.0f;
   a.out_sign = reversed ? -1.0f : 1.0f;
@@ -643,7 +700,7 @@ extern "C" dgrtm_status dgrtm_profile_start(dgrtm_shot sh, int sample_every) {
 
 extern "C" dgrtm_status dgrtm_profile_read(dgrtm_shot sh, int mode, double *kernel_ms, int64_t *launches,
                                            int64_t *element_steps) {
-  if (!sh || mode < 0 || mode > 3) return fail(DGRTM_ERR_ARG, "dgrtm_profile_read: bad argument");
+  if (!sh || mode < 0 || mode > 4) return fail(DGRTM_ERR_ARG, "dgrtm_profile_read: bad argument");
   HIPCHK(hipStreamSynchronize(sh->mesh->stream));
   double ms = 0.0;
   int64_t n = 0, es = 0;
@@ -702,7 +759,28 @@ static SlotArgs phase_slot(dgrtm_shot sh, int &mode, bool &reversed, Field *&fie
     s.g0 = sh->g0;
     s.g1 = sh->g1;
     s.image_from = sh->g_image_start * sh->n_local;
+    s.img_rule = sh->trapezoid ? IMG_TRAPEZOID : 0;
+    if (sh->replay) {   // both fields run backward: the source record is at the same own step
+      s.img_rule |= IMG_SAME_DIR;
+      s.image_from = 0;
+    }
     mode = MODE_IMAGE;
+    reversed = true;
+  } else if (sh->ph == DGRTM_PHASE_RECOMPUTE && sh->replay) {
+    // the source field re-simulated backward in time with the recorded boundary traces
+    field = &sh->S;
+    s = field_slot(sh, sh->S);
+    if (sh->args.has_source) with_points(s, sh->src, 2);
+    s.wavelet = sh->wavelet;
+    s.n_t = sh->n_global * sh->n_local + 1;
+    s.src_scale = -1.0f;
+    s.bnd_rec = sh->bnd_rec;
+    std::memcpy(s.bnd_off, sh->bnd_off, sizeof(s.bnd_off));
+    s.seg_q = sh->seg_q;
+    s.seg_r = sh->seg_r;
+    s.g0 = sh->g0;
+    s.g1 = sh->g1;
+    mode = MODE_REPLAY_SEG;
     reversed = true;
   } else {
     field = &sh->S;
@@ -796,6 +874,12 @@ static dgrtm_status begin_segment(dgrtm_shot sh, int64_t c) {
 static dgrtm_status begin_forward(dgrtm_shot sh) {
   dgrtm_status s;
   if ((s = zero_field(sh, sh->S))) return s;
+  if (sh->replay) {   // row 0 of the boundary record: the traces of the state at rest
+    dgrtm_mesh m = sh->mesh;
+    const int64_t row = 2 * trace_face_stride(m->ref.Nfp);
+    for (int l = 1; l <= m->hm.L; ++l)
+      HIPCHK(launch_fill_f32(sh->bnd_rec + sh->bnd_off[l - 1], m->bnd_cnt[l - 1] * row, 0.0f, m->stream));
+  }
   if ((s = record(sh, sh->S, 0))) return s;
   sh->g = 0;
   sh->forward_done = false;
@@ -803,17 +887,134 @@ static dgrtm_status begin_forward(dgrtm_shot sh) {
   return DGRTM_OK;
 }
 
+// segment gb of a replay adjoint: backward global step gb of the source field, recorded for the
+// receiver field's image step of the same global step
+static dgrtm_status begin_replay_segment(dgrtm_shot sh, int64_t gb) {
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  sh->c = gb;
+  sh->g0 = gb;
+  sh->g1 = gb + 1;
+  sh->g = gb;
+  SegInitArgs si;
+  std::memset(&si, 0, sizeof(si));
+  si.ring = sh->S.ring;
+  si.geo = m->geo;
+  si.eflag = m->eflag;
+  si.seg_r = sh->seg_r;
+  si.Ktot = h.Ktot;
+  si.L = h.L;
+  fill_level_begin(h, si.lev_begin);
+  std::memcpy(si.up, sh->up, sizeof(si.up));
+  si.condition = sh->condition;
+  si.history_before_start = 1;   // the extrapolated history of own steps -1 and -2
+  for (int l = 1; l <= h.L; ++l) {
+    si.seg_r_off[l - 1] = sh->seg_r_off[l - 1];
+    si.seg_m0[l - 1] = gb << (l - 1);
+  }
+  HIPCHK(launch_seg_init(m->ref.N, si, m->stream));
+  sh->ph = DGRTM_PHASE_RECOMPUTE;
+  return DGRTM_OK;
+}
+
+// Start of a replay adjoint: the backward source run's AB3 history at t_final, extrapolated from
+// its reversed-time rhs at the global times NG, NG - 1 and NG - 2 (the receiver field's buffers
+// serve as scratch: state, traces, and one rhs per time in its ring), then the source field at
+// its final state with own-step traces, the receiver field at rest.
+static dgrtm_status begin_replay_adjoint(dgrtm_shot sh) {
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  const int Np = m->ref.Np;
+  const int64_t K = h.Ktot, slab = (int64_t)state_row(Np) * K;
+  const int nl = sh->n_local;
+  dgrtm_status s;
+  Field &R = sh->R;
+  for (int i = 0; i < 3; ++i) {
+    const int64_t G = sh->n_global - i;
+    if (G < 0) {   // before t = 0 the source field is at rest and the source silent
+      HIPCHK(launch_fill_f32(R.ring + i * slab, slab, 0.0f, m->stream));
+      continue;
+    }
+    const float *q = i == 0 ? sh->S.q : sh->qsave[i - 1];
+    HIPCHK(hipMemcpyAsync(R.q, q, slab * 4, hipMemcpyDeviceToDevice, m->stream));
+    R.tau = i * nl;   // the backward run's local step at global time G
+    if ((s = trace_init(sh, R))) return s;
+    StepArgs a = mesh_args(m, sh->args.precision, MODE_RHS_REPLAY, true, nl);
+    a.nslots = 1;
+    a.slot[0] = field_slot(sh, R);
+    if (sh->args.has_source) with_points(a.slot[0], sh->src, 2);
+    a.slot[0].wavelet = sh->wavelet;
+    a.slot[0].n_t = sh->n_global * nl + 1;
+    a.slot[0].data_j = G * nl;
+    a.slot[0].src_scale = -1.0f;
+    a.slot[0].bnd_rec = sh->bnd_rec;
+    std::memcpy(a.slot[0].bnd_off, sh->bnd_off, sizeof(a.slot[0].bnd_off));
+    a.slot[0].rhs_out = R.ring + i * slab;
+    a.k_end = K;
+    HIPCHK(launch_step(m->ref.N, a, m->stream));
+  }
+  int64_t lb[kMaxLevels + 1];
+  fill_level_begin(h, lb);
+  HIPCHK(launch_replay_history(Np, R.ring, R.ring + slab, R.ring + 2 * slab, sh->S.ring, K, h.L, lb, m->stream));
+  sh->S.tau = 0;
+  if ((s = trace_init(sh, sh->S))) return s;
+  if ((s = zero_field(sh, R))) return s;
+  return begin_replay_segment(sh, 0);
+}
+
 static dgrtm_status begin_adjoint(dgrtm_shot sh) {
   dgrtm_mesh m = sh->mesh;
   dgrtm_status s;
   HIPCHK(launch_fill_f64(sh->img, (int64_t)m->ref.Np * m->hm.Ktot, 0.0, m->stream));
+  if (sh->replay) return begin_replay_adjoint(sh);
   if ((s = zero_field(sh, sh->R))) return s;
   return begin_segment(sh, (sh->n_global - 1) / sh->C);
 }
 
 // work before a global step of the shot's current phase
 static dgrtm_status pre_global(dgrtm_shot sh) {
-  if (sh->ph == DGRTM_PHASE_FORWARD && sh->g % sh->C == 0) return ckpt_copy(sh, sh->S, sh->g / sh->C, true);
+  if (sh->ph != DGRTM_PHASE_FORWARD) return DGRTM_OK;
+  if (sh->replay) {
+    const int64_t i = sh->n_global - 1 - sh->g;   // the state at global time g = NG - 1 - i
+    if (i == 0 || i == 1) {
+      dgrtm_mesh m = sh->mesh;
+      HIPCHK(hipMemcpyAsync(sh->qsave[i], sh->S.q, (size_t)state_row(m->ref.Np) * m->hm.Ktot * 4,
+                            hipMemcpyDeviceToDevice, m->stream));
+    }
+    return DGRTM_OK;
+  }
+  if (sh->g % sh->C == 0) return ckpt_copy(sh, sh->S, sh->g / sh->C, true);
+  return DGRTM_OK;
+}
+
+// boundary traces of the source field after its forward launch at local step tau
+static dgrtm_status record_boundary(dgrtm_shot sh, int64_t tau) {
+  dgrtm_mesh m = sh->mesh;
+  const HostMesh &h = m->hm;
+  BndRecArgs r;
+  std::memset(&r, 0, sizeof(r));
+  r.tr = sh->S.tr;
+  r.bface = m->bface;
+  r.rec = sh->bnd_rec;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    r.bnd_off[l] = sh->bnd_off[l];
+    r.bnd_cnt[l] = m->bnd_cnt[l];
+    r.bnd_begin[l] = m->bnd_begin[l];
+  }
+  // the levels updated at tau are the finest ones down to the coarsest l with tau on its grid;
+  // their faces come first in the list
+  int lmin = h.L;
+  for (int l = 1; l <= h.L; ++l)
+    if ((tau & (((int64_t)1 << (h.L - l)) - 1)) == 0) {
+      lmin = l;
+      break;
+    }
+  for (int l = lmin; l <= h.L; ++l) r.n_active += m->bnd_cnt[l - 1];
+  r.Ktot = h.Ktot;
+  r.L = h.L;
+  fill_level_begin(h, r.lev_begin);
+  r.tau = tau;
+  HIPCHK(launch_bnd_record(m->ref.N, r, m->stream));
   return DGRTM_OK;
 }
 
@@ -835,6 +1036,11 @@ static dgrtm_status post_global(dgrtm_shot sh) {
       if (sh->g == sh->g1) sh->ph = DGRTM_PHASE_BACKWARD;
       return DGRTM_OK;
     case DGRTM_PHASE_BACKWARD:
+      if (sh->replay) {   // next backward global step, down to the start of the image window
+        if (sh->c + 1 < sh->n_global - sh->g_image_start) return begin_replay_segment(sh, sh->c + 1);
+        sh->ph = DGRTM_PHASE_DONE;
+        return DGRTM_OK;
+      }
       sh->gr += 1;
       if (sh->gr == sh->gr_end) {
         if (sh->c - 1 >= sh->g_image_start / sh->C && sh->c > 0) return begin_segment(sh, sh->c - 1);
@@ -865,7 +1071,7 @@ static dgrtm_status global_step_shots(dgrtm_shot *shots, int n) {
   std::vector<bool> rev(act.size());
   std::vector<Field *> fld(act.size());
   for (int ln = 0; ln < nl; ++ln) {
-    for (int md = 0; md < 3; ++md)
+    for (int md : {(int)MODE_PLAIN, (int)MODE_RECORD_SEG, (int)MODE_REPLAY_SEG, (int)MODE_IMAGE})
       for (int prec = 0; prec < 2; ++prec) {
         std::vector<size_t> grp;
         for (size_t i = 0; i < act.size(); ++i) {
@@ -887,10 +1093,16 @@ static dgrtm_status global_step_shots(dgrtm_shot *shots, int n) {
           for (size_t i = b; i < e; ++i) {
             dgrtm_shot sh = act[grp[i]];
             a.slot[i - b] = phase_slot(sh, mode, r, f);
-            if (mode == MODE_IMAGE) a.slot[i - b].data_j = sh->n_global * nl - sh->R.tau;
+            // physical local step of a backward run's rhs (data and source samples)
+            if (mode == MODE_IMAGE || mode == MODE_REPLAY_SEG) a.slot[i - b].data_j = sh->n_global * nl - f->tau;
             fld[grp[i]] = f;
           }
           if ((s = launch_slots(first, a, ln))) return s;
+          for (size_t i = b; i < e; ++i) {
+            dgrtm_shot sh = act[grp[i]];
+            if (sh->replay && sh->ph == DGRTM_PHASE_FORWARD)
+              if ((s = record_boundary(sh, fld[grp[i]]->tau))) return s;
+          }
           for (size_t i = b; i < e; ++i) fld[grp[i]]->tau += 1;
         }
       }
@@ -917,8 +1129,11 @@ extern "C" dgrtm_status dgrtm_forward(dgrtm_shot sh, float *traces_out) {
 static dgrtm_status set_adjoint_params(dgrtm_shot sh, const float *data, int condition, const double *up,
                                        int64_t g_image_start) {
   if (!up) return fail(DGRTM_ERR_ARG, "adjoint: up vector missing");
+  const bool trap = (condition & DGRTM_IMAGE_TRAPEZOID) != 0;
+  condition &= ~DGRTM_IMAGE_TRAPEZOID;
   if (condition != DGRTM_IMAGE_PRESSURE && condition != DGRTM_IMAGE_CHARACTERISTIC)
     return fail(DGRTM_ERR_ARG, "adjoint: bad condition");
+  sh->trapezoid = trap;
   if (g_image_start < 0 || g_image_start >= sh->n_global) return fail(DGRTM_ERR_ARG, "adjoint: bad g_image_start");
   sh->data = data;
   sh->condition = condition;
@@ -971,6 +1186,20 @@ extern "C" dgrtm_status dgrtm_shot_traces(dgrtm_shot sh, float *out) {
 extern "C" dgrtm_status dgrtm_shot_state(dgrtm_shot sh, int *phase, int64_t *steps_done, int64_t *steps_total) {
   if (!sh) return fail(DGRTM_ERR_ARG, "dgrtm_shot_state: bad argument");
   const int64_t NG = sh->n_global, C = sh->C;
+  if (sh->replay) {   // forward NG, then per backward global step: source, then receiver field
+    const int64_t total = NG + 2 * (NG - sh->g_image_start);
+    int64_t done = 0;
+    switch (sh->ph) {
+      case DGRTM_PHASE_FORWARD: done = sh->g; break;
+      case DGRTM_PHASE_IDLE: done = sh->forward_done ? NG : 0; break;
+      case DGRTM_PHASE_DONE: done = total; break;
+      default: done = NG + 2 * sh->c + (sh->ph == DGRTM_PHASE_BACKWARD ? 1 : 0);
+    }
+    if (phase) *phase = sh->ph;
+    if (steps_done) *steps_done = done;
+    if (steps_total) *steps_total = total;
+    return DGRTM_OK;
+  }
   // forward NG, then per segment (recompute + backward)
   int64_t total = NG, done = 0;
   for (int64_t c = (NG - 1) / C; c >= sh->g_image_start / C; --c) {

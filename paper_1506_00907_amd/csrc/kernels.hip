@@ -72,15 +72,44 @@ __device__ __forceinline__ constexpr int lqix(int c, int n, int e) {
   return ((c * Dims<N>::NK + (n >> 2)) * 16 + e) * 4 + (n & 3);
 }
 
-// AB3 weights of the full step and of the half step, image weights for the mixed-direction
-// correlation (S forward from t_a, R backward from t_b): ebar_s = int_0^1 A_s,
-// Cmix_{s1 s2} = int_0^1 A_s1(th) A_s2(1-th), with A_s = int_0^th of the Lagrange basis on {0,-1,-2}
+// AB3 weights of the full step and of the half step
 constexpr float kA0 = 23.0f / 12.0f, kA1 = -16.0f / 12.0f, kA2 = 5.0f / 12.0f;
 constexpr float kB0 = 17.0f / 24.0f, kB1 = -7.0f / 24.0f, kB2 = 2.0f / 24.0f;
-constexpr double kE[3] = {19.0 / 24.0, -5.0 / 12.0, 1.0 / 8.0};
-constexpr double kCm[3][3] = {{3341.0 / 10080.0, -667.0 / 5040.0, 43.0 / 1120.0},
-                              {-667.0 / 5040.0, 19.0 / 420.0, -13.0 / 1008.0},
-                              {43.0 / 1120.0, -13.0 / 1008.0, 37.0 / 10080.0}};
+
+// Image weights of one own step, per rule (index IMG_SAME_DIR | IMG_TRAPEZOID): the increment is
+// dt qS qR + dt^2 sum_s E_s (qS rR_s + rS_s qR) + dt^3 sum C_{s1 s2} rS_s1 rR_s2, with A_s the
+// integral from 0 to th of the Lagrange basis on the time nodes {0, -1, -2}:
+//   exact, S forward from t_a and R backward from t_b: E_s = ebar_s = int_0^1 A_s,
+//     C = Cmix_{s1 s2} = int_0^1 A_s1(th) A_s2(1 - th);
+//   exact, both backward from t_b (boundary-trace replay): E_s = ebar_s, C = int_0^1 A_s1 A_s2
+//     (the matrix of the imaging section);
+//   trapezoid rule, dt/2 (S R at both ends), the far ends from the AB3 update: E_s = a_s / 2 and
+//     C = 0 (mixed direction) or C = a_s1 a_s2 / 2 (both backward)
+#define DGRTM_E_EXACT 19.0 / 24.0, -5.0 / 12.0, 1.0 / 8.0
+#define DGRTM_E_TRAP 23.0 / 24.0, -16.0 / 24.0, 5.0 / 24.0
+__constant__ double kImgW[4][12] = {
+    {DGRTM_E_EXACT, 3341.0 / 10080.0, -667.0 / 5040.0, 43.0 / 1120.0, -667.0 / 5040.0, 19.0 / 420.0, -13.0 / 1008.0,
+     43.0 / 1120.0, -13.0 / 1008.0, 37.0 / 10080.0},
+    {DGRTM_E_EXACT, 4703.0 / 5040.0, -457.0 / 840.0, 52.0 / 315.0, -457.0 / 840.0, 103.0 / 315.0, -251.0 / 2520.0,
+     52.0 / 315.0, -251.0 / 2520.0, 17.0 / 560.0},
+    {DGRTM_E_TRAP, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0},
+    {DGRTM_E_TRAP, 529.0 / 288.0, -368.0 / 288.0, 115.0 / 288.0, -368.0 / 288.0, 256.0 / 288.0, -80.0 / 288.0,
+     115.0 / 288.0, -80.0 / 288.0, 25.0 / 288.0}};
+#undef DGRTM_E_EXACT
+#undef DGRTM_E_TRAP
+
+// own-step index of the source-field record that an image step at receiver own step m reads
+__device__ __forceinline__ int64_t image_source_step(const SlotArgs &sl, int lev, int64_t m) {
+  return (sl.img_rule & IMG_SAME_DIR) ? m : (sl.NG << (lev - 1)) - m - 1;
+}
+
+// where a replayed boundary face's record row is: face b (its index among the boundary faces of
+// level lev), for an element at own step m of the backward run (physical own step NG 2^(lev-1) - m)
+template <int N>
+__device__ __forceinline__ const float *replay_row(const StepArgs &a, const SlotArgs &sl, int lev, int64_t m, int b) {
+  const int64_t j = (sl.NG << (lev - 1)) - m;
+  return sl.bnd_rec + sl.bnd_off[lev - 1] + (j * a.bnd_cnt[lev - 1] + b) * (2 * Dims<N>::FS);
+}
 
 // Copy nwords 32-bit words from global to LDS with the whole work-group: all 16-byte loads of a
 // thread are issued before its LDS stores, so the copy costs one memory latency.
@@ -120,6 +149,7 @@ __device__ __forceinline__ void split_bf16(float x, short &hi, short &lo) {
 struct FaceCtx {
   float nx, ny, nz, Fs, taup, tauv;
   int nb, f2;
+  int rep_b;   // replay modes: the face's index among its level's boundary faces, else -1
   const float *trp;
   const int8_t *tab;
 };
@@ -146,6 +176,7 @@ __device__ __forceinline__ FaceCtx face_ctx_of(const StepArgs &a, const SlotArgs
   c.trp = sl.tr;
   c.tab = a.nbr_index;
   c.f2 = 0;
+  c.rep_b = (nb < 0 && code >= 0) ? code : -1;
   if (c.nb >= 0) {
     c.f2 = code & 3;
     const int perm = (code >> 2) & 7;
@@ -213,6 +244,8 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
       float amp = 0.0f;
       if (sl.amp_mode == 0) {
         amp = sl.wavelet[sl.tau];
+      } else if (sl.amp_mode == 2) {
+        amp = (sl.data_j >= 0 && sl.data_j < sl.n_t) ? sl.wavelet[sl.data_j] : 0.0f;
       } else {
         const int64_t j = sl.data_j;
         const int64_t gq = j / a.n_local, rem = j % a.n_local;
@@ -291,7 +324,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
   }
   if constexpr (MODE == MODE_RECORD_SEG) jS = m - (sl.g0 << (lev - 1));
   if constexpr (MODE == MODE_IMAGE) {
-    const int64_t mS = (sl.NG << (lev - 1)) - m - 1;  // source step [t_a, t_b] of this receiver step
+    const int64_t mS = image_source_step(sl, lev, m);   // the source step this receiver step pairs with
     jS = mS - (sl.g0 << (lev - 1));
     do_img = (mS << sh) >= sl.image_from && jS >= 0 && jS < ((sl.g1 - sl.g0) << (lev - 1));
   }
@@ -407,13 +440,14 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
           const double rR[3] = {r[0] + zs * (ux * r[1] + uy * r[2] + uz * r[3]),
                                 h1[i][0] + zs * (ux * h1[i][1] + uy * h1[i][2] + uz * h1[i][3]),
                                 h2[i][0] + zs * (ux * h2[i][1] + uy * h2[i][2] + uz * h2[i][3])};
+          const double *W = kImgW[sl.img_rule & 3];
           double inc2 = 0.0, inc3 = 0.0;
 #pragma unroll
-          for (int s = 0; s < 3; ++s) inc2 += kE[s] * (qS * rR[s] + rS[s] * qR);
+          for (int s = 0; s < 3; ++s) inc2 += W[s] * (qS * rR[s] + rS[s] * qR);
 #pragma unroll
           for (int s1 = 0; s1 < 3; ++s1)
 #pragma unroll
-            for (int s2 = 0; s2 < 3; ++s2) inc3 += kCm[s1][s2] * rS[s1] * rR[s2];
+            for (int s2 = 0; s2 < 3; ++s2) inc3 += W[3 + 3 * s1 + s2] * rS[s1] * rR[s2];
           sl.img[tix(Np, n, k)] = imv[i] + dtd * (qS * qR + dtd * (inc2 + dtd * inc3));
         }
       }
@@ -616,7 +650,10 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   using DB = DimsB<N>;
   constexpr int Np = Dm::Np, Nfp = Dm::Nfp, F = Dm::F, NR = Dm::NR, NK = Dm::NK, FC = Dm::FC;
   constexpr int QW = DD::QW;
-  constexpr bool HIST = MODE != MODE_RHS_ONLY;
+  // the replay modes are the record and rhs-only modes with replayed boundary faces
+  constexpr bool REPLAY = MODE == MODE_REPLAY_SEG || MODE == MODE_RHS_REPLAY;
+  constexpr int BM = base_mode(MODE);
+  constexpr bool HIST = BM != MODE_RHS_ONLY;
   // LIFT fragments: FP32 [NR][4 FC][64] floats, or split-BF16 [NR][4 FC_B][64] x (4 hi + 4 lo) bf16
   constexpr int SLW = PREC ? NR * 4 * DB::FC * 64 * 4 : NR * 4 * FC * 64;
   __shared__ __align__(16) uint32_t stabw[Dm::TABW];
@@ -669,18 +706,33 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   auto issue_g = [&](int64_t t) { copy_block<kGeo>(a.geo + tix(kGeo, 0, t * 16), lg, lane); };
   // a tile's neighbours' face runs (nb, cd: the tile's neighbour ids and codes)
   auto issue_t = [&](int64_t t, const int (&nbs)[4], const int (&cds)[4]) {
+    int lev_t = 0;
+    int64_t m_t = 0;
+    if constexpr (REPLAY) {
+      lev_t = level_of(a.lev_begin, a.L, t * 16);
+      m_t = sl.tau >> (a.L - lev_t);
+    }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       const int nb = nbs[f], code = cds[f];
       const int f2 = code & 3, perm = (code >> 2) & 7, shn = a.L - (code >> 5);
       const int slot = nb >= 0 ? (((sl.tau & ((1LL << shn) - 1)) == 0) ? (int)((sl.tau >> shn) & 1) : 2) : 0;
       const float *trp = sl.tr + (int64_t)slot * Dm::TRS * K;
+      // a replayed boundary face: its recorded run, in the element's own node order
+      const bool rep = REPLAY && nb < 0 && code >= 0;
       // lane (g, e) copies nodes 4g .. 4g+3 of the neighbour's face run (in the neighbour's node
       // order) to [face][component][g][e][4]; the surface terms apply the node permutation
-      if (nb >= 0 && 4 * g < Dm::FS) {
-        const float *run = trp + (int64_t)nb * Dm::TRS + f2 * Dm::FS + 4 * g;
+      if ((nb >= 0 || rep) && 4 * g < Dm::FS) {
+        const float *run, *run2;
+        if (rep) {
+          run = replay_row<N>(a, sl, lev_t, m_t, code) + 4 * g;
+          run2 = run + Dm::FS;
+        } else {
+          run = trp + (int64_t)nb * Dm::TRS + f2 * Dm::FS + 4 * g;
+          run2 = run + Dm::TRC;
+        }
         lds_copy16(run, ln + 4 * (2 * f + 0) * 16 * Dm::FS);
-        lds_copy16(run + Dm::TRC, ln + 4 * (2 * f + 1) * 16 * Dm::FS);
+        lds_copy16(run2, ln + 4 * (2 * f + 1) * 16 * Dm::FS);
       }
       (void)perm;
     }
@@ -748,7 +800,7 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
   //            this tile no longer reads
   //   end      traces of the new state; the next tile's state (and, for the image step, geometry
   //            and neighbour runs); then the SW block stores of the new state and the new rhs
-  constexpr bool EARLY_GT = HIST && MODE != MODE_IMAGE;
+  constexpr bool EARLY_GT = HIST && BM != MODE_IMAGE;
   constexpr int SW = HIST ? 2 * NK : 0;   // 16 NK rows per block store: NK instructions each
 
   while (true) {
@@ -863,7 +915,9 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       // with p_nb, (n.v)_nb the neighbour's traces on an interior face and 0 on a boundary face;
       // cP = 1 on a rigid wall, -1 on a free surface, 0 on a transparent or interior face
       const bool inner = nb >= 0;
-      const float cP = nb == -1 ? 1.0f : (nb == -3 ? -1.0f : 0.0f);
+      // a replayed boundary face takes its whole exterior state from the record
+      const bool rep = REPLAY && !inner && codev[f] >= 0;
+      const float cP = REPLAY ? 0.0f : (nb == -1 ? 1.0f : (nb == -3 ? -1.0f : 0.0f));
       const int f2 = inner ? (codev[f] & 3) : 0, perm = inner ? ((codev[f] >> 2) & 7) : 0;
       v4f G[NR];
 #pragma unroll
@@ -873,10 +927,10 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
         const float pm = q_t[lqix<N>(0, node, e)];
         const float nvm = nx * q_t[lqix<N>(1, node, e)] + ny * q_t[lqix<N>(2, node, e)] + nz * q_t[lqix<N>(3, node, e)];
         // the neighbour's node matching face node s of this face
-        const int t = stab[((f * 4 + f2) * 6 + perm) * Nfp + min(s, Nfp - 1)];
+        const int t = rep ? min(s, Nfp - 1) : stab[((f * 4 + f2) * 6 + perm) * Nfp + min(s, Nfp - 1)];
         const int toff = (t >> 2) * 64 + e * 4 + (t & 3);
-        const float tp = inner ? n_t[(2 * f + 0) * 16 * Dm::FS + toff] : 0.0f;
-        const float tv = inner ? n_t[(2 * f + 1) * 16 * Dm::FS + toff] : 0.0f;
+        const float tp = (inner || rep) ? n_t[(2 * f + 0) * 16 * Dm::FS + toff] : 0.0f;
+        const float tv = (inner || rep) ? n_t[(2 * f + 1) * 16 * Dm::FS + toff] : 0.0f;
         const float pp = cP * pm + tp;
         const float nvp = -(cP * nvm + tv);
         const float dp = pp - pm, dnv = nvp - nvm;
@@ -934,11 +988,11 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
     }
     const float *sseg = nullptr;
     double imv[NR * 4];   // the image at this lane's nodes (image step), loaded with the segment rows
-    if constexpr (MODE == MODE_IMAGE) {
+    if constexpr (BM == MODE_IMAGE) {
       // the source-wavefield segment rows this receiver step correlates with go to the geometry
       // and neighbour-trace tiles, which the tile no longer reads
       static_assert(4 * Np * 16 <= DD::GW + DD::TW, "segment rows fit in the geometry and trace tiles");
-      const int64_t mS = (sl.NG << (lev - 1)) - m - 1;
+      const int64_t mS = image_source_step(sl, lev, m);
       const int64_t jS = mS - (sl.g0 << (lev - 1));
       if ((mS << sh) >= sl.image_from && jS >= 0 && jS < ((sl.g1 - sl.g0) << (lev - 1))) {
         int64_t oq, orr;
@@ -975,9 +1029,9 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
       if (more) issue_gt(nxt, nbn, coden);
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE, true, HIST, HIST, MODE == MODE_IMAGE>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy,
-                                                          nfz, rp, rvx, rvy, rvz, h_t, h_t + QW, sseg,
-                                                          MODE == MODE_IMAGE ? imv : nullptr);
+    tile_tail<N, BM, true, HIST, HIST, BM == MODE_IMAGE>(a, sl, k, g, lev, sh, m, flag, q_t, e, gg[11], nfx, nfy,
+                                                        nfz, rp, rvx, rvy, rvz, h_t, h_t + QW, sseg,
+                                                        BM == MODE_IMAGE ? imv : nullptr);
     if constexpr (HIST) {
       tile_traces<N>(a, sl, k, g, e, m, flag, h_t, q_t, nfx, nfy, nfz);
       // the old-state tile (half-step state by now) and, for the image step, the segment rows in
@@ -1042,6 +1096,9 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   constexpr int QW = DD::QW, GW = DD::GW;
   // N = 6 has no registers to spare: one volume chunk at a time, neighbour traces read per chunk
   constexpr bool LEAN = N >= 6;
+  // the replay modes are the record and rhs-only modes with replayed boundary faces
+  constexpr bool REPLAY = MODE == MODE_REPLAY_SEG || MODE == MODE_RHS_REPLAY;
+  constexpr int BM = base_mode(MODE);
   constexpr int VU = LEAN ? 1 : 2;
   extern __shared__ __align__(16) float sdyn[];   // [operators if OPS_LDS][4 wavefronts][QW + GW]
   __shared__ __align__(16) uint32_t stabw[Dm::TABW];   // face-node map [4][4][6][Nfp]
@@ -1197,6 +1254,14 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
                          tab[inner ? min(4 * cc + g, Nfp - 1) : 0];
       p_ = inner ? nbt[0] : 0.0f;
       v_ = inner ? nbt[Dm::TRC] : 0.0f;
+      if constexpr (REPLAY) {
+        if (fc.rep_b >= 0) {   // a replayed boundary face: the recorded run, own node order
+          const float *row = replay_row<N>(a, sl, lev, m, fc.rep_b);
+          const int sidx = min(4 * cc + g, Nfp - 1);
+          p_ = row[sidx];
+          v_ = row[Dm::FS + sidx];
+        }
+      }
     };
     float tpa[4][FC], tva[4][FC];
     if constexpr (!LEAN && PREC == 0) {
@@ -1209,8 +1274,9 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     for (int f = 0; f < 4; ++f) {
       const FaceCtx &fc = fcs[f];
       nfx[f] = fc.nx; nfy[f] = fc.ny; nfz[f] = fc.nz;
-      // boundary states without branches (cP = 1 rigid wall, -1 free surface, 0 otherwise)
-      const float cP = fc.nb == -1 ? 1.0f : (fc.nb == -3 ? -1.0f : 0.0f);
+      // boundary states without branches (cP = 1 rigid wall, -1 free surface, 0 otherwise; 0 on
+      // every face when the boundary faces are replayed)
+      const float cP = REPLAY ? 0.0f : (fc.nb == -1 ? 1.0f : (fc.nb == -3 ? -1.0f : 0.0f));
       float (&tp)[FC] = tpa[f];
       float (&tv)[FC] = tva[f];
       v4f G[NR];
@@ -1252,7 +1318,14 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
                                   T.fmask[f][min(16 * cc + 8 + v, Nfp - 1)], T.fmask[f][min(16 * cc + 12 + v, Nfp - 1)]);
             const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::FS +
                                tab[inner ? min(s, Nfp - 1) : 0];
-            const float tps = inner ? nbt[0] : 0.0f, tvs = inner ? nbt[Dm::TRC] : 0.0f;
+            float tps = inner ? nbt[0] : 0.0f, tvs = inner ? nbt[Dm::TRC] : 0.0f;
+            if constexpr (REPLAY) {
+              if (fc.rep_b >= 0) {
+                const float *row = replay_row<N>(a, sl, lev, m, fc.rep_b);
+                tps = row[min(s, Nfp - 1)];
+                tvs = row[Dm::FS + min(s, Nfp - 1)];
+              }
+            }
             const float pm = q_t[lqix<N>(0, node, e)];
             const float nvm = fc.nx * q_t[lqix<N>(1, node, e)] + fc.ny * q_t[lqix<N>(2, node, e)] +
                               fc.nz * q_t[lqix<N>(3, node, e)];
@@ -1283,10 +1356,10 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, MODE, true, false, false, false, MODE != MODE_RHS_ONLY>(a, sl, k, g, lev, sh, m, flag, q_t, e,
-                                                                        gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
+    tile_tail<N, BM, true, false, false, false, BM != MODE_RHS_ONLY>(a, sl, k, g, lev, sh, m, flag, q_t, e,
+                                                                    gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
     // own-step traces of the new state (now in the state tile); the half-step ones went out per lane
-    if constexpr (MODE != MODE_RHS_ONLY) tile_traces<N, false>(a, sl, k, g, e, m, flag, q_t, nullptr, nfx, nfy, nfz);
+    if constexpr (BM != MODE_RHS_ONLY) tile_traces<N, false>(a, sl, k, g, e, m, flag, q_t, nullptr, nfx, nfy, nfz);
     const int64_t nn = dyn ? 2 * nfirst + __builtin_amdgcn_readfirstlane(vnn) : nxt + nfirst;
     // every LDS read of this tile is done: the next tile's copies may land
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -1364,13 +1437,52 @@ __global__ __launch_bounds__(256) void seg_init_kernel(const SegInitArgs a) {
     const float *R = a.ring + ((ms % 3 + 3) % 3) * slab;
     for (int n = 0; n < Np; ++n) {
       float v = 0.0f;
-      if (ms >= 0) {
+      if (ms >= 0 || a.history_before_start) {
         const float r0 = R[qix(node_quads(Np), 0, n, k)], r1 = R[qix(node_quads(Np), 1, n, k)];
         const float r2 = R[qix(node_quads(Np), 2, n, k)], r3 = R[qix(node_quads(Np), 3, n, k)];
         v = r0 - zs * (a.up[0] * r1 + a.up[1] * r2 + a.up[2] * r3);
       }
       a.seg_r[a.seg_r_off[lev - 1] + (2 - s) * Np * Pl + tix(Np, n, kk)] = v;
     }
+  }
+}
+
+// one thread per 16-byte chunk of a boundary face's record row (FS / 4 chunks of p, then of -n.v)
+template <int N>
+__global__ __launch_bounds__(256) void bnd_record_kernel(const BndRecArgs a) {
+  constexpr int FS = Dims<N>::FS, TRC = Dims<N>::TRC, TRS = Dims<N>::TRS, CH = FS / 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_active * 2 * CH) return;
+  const int64_t i = t / (2 * CH);
+  const int comp = (int)(t % (2 * CH)) / CH, c = (int)(t % CH);
+  const int sf = a.bface[i];
+  const int64_t k = sf >> 2;
+  const int f = sf & 3;
+  const int lev = level_of(a.lev_begin, a.L, k);
+  const int64_t j = (a.tau >> (a.L - lev)) + 1;   // own step reached by the launch at tau
+  const float4 v = *reinterpret_cast<const float4 *>(a.tr + (j & 1) * (int64_t)TRS * a.Ktot + k * TRS + comp * TRC +
+                                                     f * FS + 4 * c);
+  const float sg = comp ? -1.0f : 1.0f;
+  const int64_t b = i - a.bnd_begin[lev - 1];
+  float *dst = a.rec + a.bnd_off[lev - 1] + (j * a.bnd_cnt[lev - 1] + b) * (2 * FS) + comp * FS + 4 * c;
+  *reinterpret_cast<float4 *>(dst) = float4{sg * v.x, sg * v.y, sg * v.z, sg * v.w};
+}
+
+// the quadratic through r0, r1, r2 (the reversed-time rhs at t_f, t_f - dt_g, t_f - 2 dt_g),
+// evaluated at t_f + dt_l and t_f + 2 dt_l (dt_l / dt_g = 2^(1 - l) for level l): ring slots 2, 1
+__global__ __launch_bounds__(256) void replay_history_kernel(const float *r0, const float *r1, const float *r2,
+                                                             float *ring, int64_t slab, int64_t tile_floats,
+                                                             int L, ReplayLevels lb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= slab) return;
+  const int lev = level_of(lb.lev_begin, L, (i / tile_floats) * 16);
+  const double x0 = r0[i], x1 = r1[i], x2 = r2[i];
+  const double rho = 1.0 / (double)(1LL << (lev - 1));
+#pragma unroll
+  for (int k = 1; k <= 2; ++k) {
+    const double tau = k * rho;   // in units of dt_g after t_f
+    const double l0 = 0.5 * (tau + 1.0) * (tau + 2.0), l1 = -tau * (tau + 2.0), l2 = 0.5 * tau * (tau + 1.0);
+    ring[(k == 1 ? 2 : 1) * slab + i] = (float)(l0 * x0 + l1 * x1 + l2 * x2);
   }
 }
 
@@ -1500,6 +1612,8 @@ static hipError_t launch_step_n(const StepArgs &a, hipStream_t st) {
     case MODE_IMAGE: return launch_step_mode<N, MODE_IMAGE>(a, st);
     case MODE_RECORD_SEG: return launch_step_mode<N, MODE_RECORD_SEG>(a, st);
     case MODE_PLAIN: return launch_step_mode<N, MODE_PLAIN>(a, st);
+    case MODE_REPLAY_SEG: return launch_step_mode<N, MODE_REPLAY_SEG>(a, st);
+    case MODE_RHS_REPLAY: return launch_step_mode<N, MODE_RHS_REPLAY>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1664,6 +1778,32 @@ hipError_t launch_residual(const float *a, const float *b, int64_t n, double *ou
   if (n <= 0) return hipSuccess;
   unsigned nb = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
   hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(256), 0, st, a, b, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_bnd_record(int N, const BndRecArgs &a, hipStream_t st) {
+  if (a.n_active <= 0) return hipSuccess;
+  auto go = [&](auto kern, int FS) {
+    hipLaunchKernelGGL(kern, dim3(blocks_for(a.n_active * 2 * (FS / 4), 256)), dim3(256), 0, st, a);
+  };
+  switch (N) {
+    case 1: go(bnd_record_kernel<1>, Dims<1>::FS); break;
+    case 2: go(bnd_record_kernel<2>, Dims<2>::FS); break;
+    case 3: go(bnd_record_kernel<3>, Dims<3>::FS); break;
+    case 4: go(bnd_record_kernel<4>, Dims<4>::FS); break;
+    case 5: go(bnd_record_kernel<5>, Dims<5>::FS); break;
+    case 6: go(bnd_record_kernel<6>, Dims<6>::FS); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_replay_history(int Np, const float *r0, const float *r1, const float *r2, float *ring, int64_t Ktot,
+                                 int L, const int64_t *lev_begin, hipStream_t st) {
+  const int64_t slab = (int64_t)state_row(Np) * Ktot;
+  if (slab <= 0) return hipSuccess;
+  ReplayLevels lb;
+  for (int i = 0; i <= kMaxLevels; ++i) lb.lev_begin[i] = lev_begin[i];
+  hipLaunchKernelGGL(replay_history_kernel, dim3(blocks_for(slab, 256)), dim3(256), 0, st, r0, r1, r2, ring, slab,
+                     (int64_t)16 * state_row(Np), L, lb);
   return hipGetLastError();
 }
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st) {

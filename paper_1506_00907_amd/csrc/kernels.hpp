@@ -23,7 +23,20 @@ namespace dgrtm {
 constexpr int kGeo = 20;
 constexpr int kMaxLevels = 8;
 
-enum StepMode : int { MODE_PLAIN = 0, MODE_RECORD_SEG = 1, MODE_IMAGE = 2, MODE_RHS_ONLY = 3 };
+// MODE_REPLAY_SEG and MODE_RHS_REPLAY are MODE_RECORD_SEG and MODE_RHS_ONLY for the source field
+// re-simulated backward in time: every boundary face takes its exterior state from the boundary
+// traces recorded by the forward run (SlotArgs::bnd_rec) instead of its boundary condition
+enum StepMode : int {
+  MODE_PLAIN = 0, MODE_RECORD_SEG = 1, MODE_IMAGE = 2, MODE_RHS_ONLY = 3, MODE_REPLAY_SEG = 4, MODE_RHS_REPLAY = 5
+};
+__host__ __device__ constexpr int base_mode(int mode) {
+  return mode == MODE_REPLAY_SEG ? MODE_RECORD_SEG : (mode == MODE_RHS_REPLAY ? MODE_RHS_ONLY : mode);
+}
+
+// image rules (SlotArgs::img_rule): bit 0 the source field runs backward too (boundary-trace
+// replay) rather than forward from a checkpoint, bit 1 the trapezoid rule instead of the exact
+// integral of the dense outputs
+constexpr int IMG_SAME_DIR = 1, IMG_TRAPEZOID = 2;
 
 constexpr int kMaxSlots = 8;
 
@@ -58,7 +71,8 @@ struct SlotArgs {
   const int *src_count;               // [Ktot]
   const int *src_point;               // entries -> point id
   const float *src_w;                 // [n_points][Np] projected-delta weights
-  const float *wavelet;               // amp_mode 0: source signal at every local step
+  const float *wavelet;               // amp_mode 0: source signal at every local step (at local step
+                                      // tau; amp_mode 2: at physical local step data_j, n_t samples)
   const float *data;                  // amp_mode 1: [n_points][n_t] samples at global steps
   float *seg_q, *seg_r;               // segment buffer: per level [C N_l][Np][P_l] and [C N_l + 2][Np][P_l]
   double *img;                        // [Np][Ktot]
@@ -71,8 +85,13 @@ struct SlotArgs {
   int64_t image_from;                 // image only where the source step starts at or after this local step
   float up[3];
   float src_scale;
-  int amp_mode;                       // 0 wavelet table, 1 linear data interpolation
+  int amp_mode;                       // 0 wavelet table, 1 linear data interpolation, 2 wavelet at data_j
   int condition;                      // 0 pressure, 1 characteristic
+  int img_rule;                       // IMG_SAME_DIR | IMG_TRAPEZOID bits (MODE_IMAGE)
+  // boundary-trace record (replay modes): level l's rows at bnd_rec + bnd_off[l-1], row j b of
+  // boundary face b at own step j, 2 FS floats: p, then -n.v (as a neighbour would see it)
+  const float *bnd_rec;
+  int64_t bnd_off[kMaxLevels];
 };
 
 struct StepArgs {
@@ -90,6 +109,8 @@ struct StepArgs {
   int64_t Ktot;
   int L;                              // number of levels
   int64_t lev_begin[kMaxLevels + 1];  // index l-1 -> first position of level l (finest first)
+  int64_t bnd_cnt[kMaxLevels];        // boundary faces of level l (index l-1); ncode of a boundary
+                                      // face holds its index among them, -1 on padding elements
   // launch
   int64_t k_end;                      // active prefix (multiple of 64), the same for every slot
   int64_t max_groups;                 // cap on work-groups along x; 0 = none
@@ -147,8 +168,34 @@ struct SegInitArgs {
   int64_t lev_begin[kMaxLevels + 1];
   float up[3];
   int condition;
+  int history_before_start;           // the ring holds history for own steps -1, -2 (backward replay run)
 };
 hipError_t launch_seg_init(int N, const SegInitArgs &a, hipStream_t st);
+// boundary traces of the source field after a forward local step: for the boundary faces of the
+// levels updated by the launch at local step tau (a prefix of the face list, finest level first),
+// p and -n.v of own step j = tau / 2^(L-l) + 1, from trace slot j mod 2, into row j of the record
+struct BndRecArgs {
+  const float *tr;
+  const int *bface;                   // [n_faces] sorted element position * 4 + face, finest first
+  float *rec;
+  int64_t bnd_off[kMaxLevels];        // level l's rows at rec + bnd_off[l-1]
+  int64_t bnd_cnt[kMaxLevels];
+  int64_t bnd_begin[kMaxLevels];      // index in bface of level l's first face
+  int64_t n_active;                   // faces of the updated levels
+  int64_t Ktot;
+  int L;
+  int64_t lev_begin[kMaxLevels + 1];
+  int64_t tau;
+};
+hipError_t launch_bnd_record(int N, const BndRecArgs &a, hipStream_t st);
+struct ReplayLevels {
+  int64_t lev_begin[kMaxLevels + 1];
+};
+// AB3 history of the backward source run at its start: r(-dt_l) into ring slot 2 and r(-2 dt_l)
+// into slot 1, from the quadratic through the reversed-time rhs r0, r1, r2 at the global times
+// t_f, t_f - dt_g, t_f - 2 dt_g, evaluated at t_f + dt_l and t_f + 2 dt_l
+hipError_t launch_replay_history(int Np, const float *r0, const float *r1, const float *r2, float *ring, int64_t Ktot,
+                                 int L, const int64_t *lev_begin, hipStream_t st);
 // sum over all entries of (a - b)^2 in FP64 into out[0] (out zeroed by the caller)
 hipError_t launch_residual(const float *a, const float *b, int64_t n, double *out, hipStream_t st);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);

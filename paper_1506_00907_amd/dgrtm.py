@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libdgrtm.so")
 
 BC_RIGID, BC_TRANSPARENT, BC_FREE = 1, 2, 3
 IMAGE_PRESSURE, IMAGE_CHARACTERISTIC = 0, 1
+IMAGE_TRAPEZOID = 0x100
 FP32, SPLIT_BF16 = 0, 1
+STORE_CHECKPOINTS, STORE_BOUNDARY = 0, 1
 SOURCE_FIELD, RECEIVER_FIELD = 0, 1
 PHASE_IDLE, PHASE_FORWARD, PHASE_RECOMPUTE, PHASE_BACKWARD, PHASE_DONE = 0, 1, 2, 3, 4
 
@@ -65,7 +67,7 @@ class ShotArgs(C.Structure):
                 ("f_peak", C.c_double), ("t_peak", C.c_double), ("amp", C.c_double),
                 ("wavelet", C.c_void_p), ("n_rec", C.c_int64), ("rec_xyz", C.c_void_p),
                 ("t_final", C.c_double), ("ckpt_interval", C.c_int64), ("precision", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("storage", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -230,6 +232,7 @@ class ShotSpec:
     wavelet: np.ndarray | None = None
     ckpt_interval: int = 0
     precision: int = 0
+    storage: int = 0
 
 
 class Shot:
@@ -256,6 +259,7 @@ class Shot:
         a.t_final = float(spec.t_final)
         a.ckpt_interval = int(spec.ckpt_interval)
         a.precision = int(spec.precision)
+        a.storage = int(spec.storage)
         self.args = a
         ng, nl = C.c_int64(), C.c_int32()
         _check(_lib.dgrtm_shot_steps(mesh.h, C.byref(a), C.byref(ng), C.byref(nl)), "dgrtm_shot_steps")
