@@ -45,10 +45,12 @@ def bytes_per_element_step(Np: int, Nfp: int, mode: int) -> int:
     plain: q read + write (8 Np), rhs ring 2 reads + 1 write (12 Np), neighbour traces in and
     own traces out (2 x 2 x 4 Nfp), geometry/material (20), neighbour ids and codes (8), flags (1).
     record: + q-_S and r-_S written (2 Np).  image: + q-_S and 3 r-_S read (4 Np) and the FP64
-    image read and written (4 Np in float units).
+    image read and written (4 Np in float units).  replay (mode 4, the source field backward with
+    recorded boundary traces): as record; a boundary face reads its recorded run where an interior
+    face reads its neighbour's.
     """
     words = 20 * Np + 16 * Nfp + 29
-    if mode == 1:
+    if mode in (1, 4):
         words += 2 * Np
     if mode == 2:
         words += 8 * Np
@@ -264,7 +266,7 @@ def traffic_from_pmc(workload: str, fetch_dir: str, write_dir: str, copy_fetch_d
 
     sf, kf = copy_scale(copy_fetch_dir)
     sw, kw = copy_scale(copy_write_dir)
-    names = {0: "forward_step", 1: "recompute_step", 2: "image_step"}
+    names = {0: "forward_step", 1: "recompute_step", 2: "image_step", 4: "replay_step"}
     per = {}
     for d, scale, key in ((fetch_dir, sf, "fetch"), (write_dir, sw, "write")):
         for r in rows(d):
@@ -290,6 +292,51 @@ def traffic_from_pmc(workload: str, fetch_dir: str, write_dir: str, copy_fetch_d
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     return path
+
+
+def mfma_from_pmc(pmc_dir: str, trace_dir: str) -> str:
+    """Matrix-core use of the FP32 step kernels from one rocprofv3 --pmc run of SQ_VALU_MFMA_BUSY_CYCLES,
+    SQ_BUSY_CU_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_F32 and GRBM_GUI_ACTIVE (per-dispatch averages), with
+    the kernel durations from a --kernel-trace run of the same command.  One MOPS is 512 FLOP; the
+    FP32 matrix peak is 157.3 TFLOP/s; GRBM_GUI_ACTIVE is summed over the 8 XCDs."""
+    import csv
+    import glob
+
+    def rows(d, pat):
+        f = glob.glob(os.path.join(d, "**", pat), recursive=True)
+        if not f:
+            raise FileNotFoundError(f"no {pat} under {d}")
+        out = []
+        for path in f:
+            out += list(csv.DictReader(open(path)))
+        return out
+
+    dur = {}
+    for r in rows(trace_dir, "*kernel_trace.csv"):
+        dur.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    cnt = {}
+    for r in rows(pmc_dir, "*counter_collection.csv"):
+        n = r["Kernel_Name"]
+        if "step_kernel" not in n:
+            continue
+        targs = [t.strip() for t in n.split("<")[1].split(">")[0].split(",")]
+        if targs[-1] not in ("0", "false"):
+            continue
+        cnt.setdefault(n, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = [f"{'kernel':<44} {'disp':>5} {'dur_us':>8} {'MFMA_TFLOP/s':>12} {'of_peak':>8} {'MFMA_busy/SIMD':>15} "
+             f"{'CU_busy':>8}"]
+    for n, c in sorted(cnt.items()):
+        avg = {k: sum(v) / len(v) for k, v in c.items()}
+        d = dur.get(n)
+        if not d:
+            continue
+        du = sum(d) / len(d)
+        tf = avg["SQ_INSTS_VALU_MFMA_MOPS_F32"] * 512.0 / (du * 1e-6) / 1e12
+        act = avg["GRBM_GUI_ACTIVE"] / 8.0
+        lines.append(f"{n.split('(')[0].replace('void ', ''):<44} {len(c['GRBM_GUI_ACTIVE']):>5} {du:>8.1f} {tf:>12.1f} "
+                     f"{tf / 157.3:>8.3f} {avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (1024 * act):>15.3f} "
+                     f"{avg['SQ_BUSY_CU_CYCLES'] / (256 * act):>8.3f}")
+    return "\n".join(lines)
 
 
 def kernel_trace_summary(trace_dir: str, levels: int) -> str:
@@ -360,6 +407,10 @@ def main():
                     help="simulated time of the split-BF16 vs FP32 comparison shot (0 = skip, <0 = per workload)")
     ap.add_argument("--secondary", default="rtm_200k", help="second workload reported after the main one ('' = skip)")
     ap.add_argument("--secondary-t-final", type=float, default=0.25)
+    ap.add_argument("--storage", choices=["checkpoints", "boundary"], default="checkpoints",
+                    help="how the main workload's shots keep the source wavefield for the backward run")
+    ap.add_argument("--no-replay-compare", action="store_true",
+                    help="skip the boundary-replay vs checkpoint comparison on the secondary workload")
     ap.add_argument("--serving", type=int, default=64, help="requests in the serving section (0 = skip)")
     ap.add_argument("--serving-t-final", type=float, default=0.01)
     ap.add_argument("--traffic-from-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -368,7 +419,12 @@ def main():
     ap.add_argument("--kernel-trace-summary", metavar="TRACE_DIR",
                     help="print the per-kernel summary of a rocprofv3 --kernel-trace CSV run and exit")
     ap.add_argument("--levels", type=int, default=0, help="LTS levels of the traced workload (with --kernel-trace-summary)")
+    ap.add_argument("--mfma-from-pmc", nargs=2, metavar=("PMC_DIR", "TRACE_DIR"),
+                    help="print the matrix-core use of the FP32 step kernels from rocprofv3 runs and exit")
     args = ap.parse_args()
+    if args.mfma_from_pmc:
+        print(mfma_from_pmc(*args.mfma_from_pmc))
+        return
     if args.kernel_trace_summary:
         lv = args.levels or SHOT_SHAPES.get(args.workload, SHOT_SHAPES["default"])["levels"]
         print(kernel_trace_summary(args.kernel_trace_summary, lv))
@@ -386,7 +442,8 @@ def main():
 
     from paper_1506_00907_amd import dgrtm, inputs as I
 
-    out, ctx = run_workload(dgrtm, I, args.workload, args.t_final, args.steps, args.warmup, args.sample_every)
+    out, ctx = run_workload(dgrtm, I, args.workload, args.t_final, args.steps, args.warmup, args.sample_every,
+                            storage=1 if args.storage == "boundary" else 0)
     mesh, mm, rho, c, N, shape, esteps_global, dof = ctx
     if args.bf16_t_final != 0:
         bt = shape["bf16_t_final"] if args.bf16_t_final < 0 else args.bf16_t_final
@@ -397,12 +454,26 @@ def main():
     torch.cuda.empty_cache()
     if args.secondary and args.secondary != args.workload:
         log(f"secondary block: {args.secondary} ...")
-        sec, sctx = run_workload(dgrtm, I, args.secondary, args.secondary_t_final, 2, 1, args.sample_every)
         keep = ("value", "unit", "ms_per_step", "steps", "warmup", "config", "images_per_hour",
                 "single_rate_equivalent_GDOF_steps_s", "roofline")
+        imgs = []
+        sec, sctx = run_workload(dgrtm, I, args.secondary, args.secondary_t_final, 2, 1, args.sample_every,
+                                 keep_image=imgs)
         out["secondary"] = {k: sec[k] for k in keep}
         del sctx
         torch.cuda.empty_cache()
+        if not args.no_replay_compare:
+            log(f"secondary block with boundary-trace replay: {args.secondary} ...")
+            rep_, rctx = run_workload(dgrtm, I, args.secondary, args.secondary_t_final, 2, 1, args.sample_every,
+                                      storage=1, keep_image=imgs)
+            blk = {k: rep_[k] for k in keep}
+            # both images approximate the same integral; they differ by the re-simulated source
+            # field's departure from the forward one (the backward run cannot undo the upwind
+            # dissipation of the forward run)
+            blk["image_rel_l2_vs_checkpointed"] = float(np.linalg.norm(imgs[1] - imgs[0]) / np.linalg.norm(imgs[0]))
+            out["secondary_boundary_replay"] = blk
+            del rctx
+            torch.cuda.empty_cache()
     if args.serving > 0:
         log(f"serving: {args.serving} requests ...")
         out["serving"] = serving_bench(args.serving, args.serving_t_final)
@@ -413,7 +484,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_workload(dgrtm, I, workload, t_final, steps, warmup, sample_every):
+def run_workload(dgrtm, I, workload, t_final, steps, warmup, sample_every, storage=0, keep_image=None):
     """Set up one workload's mesh and shot, run warmup + timed shots, and return the result
     dict (metric line fields) and the context the later sections reuse."""
     import numpy as np
@@ -431,7 +502,7 @@ def run_workload(dgrtm, I, workload, t_final, steps, warmup, sample_every):
     src_xy = shape.get("src_xy", (0.7797, 1.0))
     spec = I.rtm_shot(box=mm.box, src_xy=src_xy, n_rec=shape["n_rec"], t_final=t_final)
     shot = dgrtm.Shot(mesh, dgrtm.ShotSpec(t_final=spec.t_final, src=spec.src, f_peak=spec.f_peak,
-                                           t_peak=spec.t_peak, rec=spec.rec))
+                                           t_peak=spec.t_peak, rec=spec.rec, storage=storage))
     lev = mesh.export_setup()["level"].astype(np.int64)
     L = mesh.L
     hist = np.bincount(lev, minlength=L + 1)[1:]
@@ -466,12 +537,12 @@ def run_workload(dgrtm, I, workload, t_final, steps, warmup, sample_every):
         log(f"timed shot {len(lat) - 1}: {lat[-1]:.2f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = {m: shot.profile_read(m) for m in (0, 1, 2)}
+    prof = {m: shot.profile_read(m) for m in (0, 1, 2, 4)}
     # element-steps per shot: forward + recompute + backward, each over every global step
     es_shot = 3 * ng * esteps_global
     value = es_shot * steps * dof / wall / 1e9
     sr_equiv = 3 * ng * mesh.K * 2 ** (L - 1) * steps * dof / wall / 1e9
-    mode_names = {0: "forward_step", 1: "recompute_step", 2: "image_step"}
+    mode_names = {0: "forward_step", 1: "recompute_step", 2: "image_step", 4: "replay_step"}
     rl = {}
     for m, p in prof.items():
         if p["launches"] == 0:
@@ -500,6 +571,7 @@ def run_workload(dgrtm, I, workload, t_final, steps, warmup, sample_every):
                    "level_histogram_coarse_to_fine": [int(x) for x in hist], "global_steps": int(ng),
                    "t_final_s": round(ng * mesh.dt_local * 2 ** (L - 1), 6), "receivers": int(shot.n_rec),
                    "image": "characteristic", "parallelism": "single GPU",
+                   "storage": "boundary traces (source re-simulated backward)" if storage else "checkpoints",
                    "shot_workspace_GB": round(shot.bytes / 1e9, 2)},
         "images_per_hour": round(3600.0 * steps / wall, 2),
         "shot_latency_s": {"p50": round(float(np.percentile(lat, 50)), 3),
@@ -513,6 +585,8 @@ def run_workload(dgrtm, I, workload, t_final, steps, warmup, sample_every):
     }
     # the timed shot's workspace (checkpoints and segment records) is released before the other
     # sections allocate theirs: on the largest meshes one shot's workspace is most of the HBM
+    if keep_image is not None:
+        keep_image.append(img.cpu().numpy())
     del shot, traces, img
     return out, (mesh, mm, rho, c, N, shape, esteps_global, dof)
 
