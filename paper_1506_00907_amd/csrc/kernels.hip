@@ -61,9 +61,10 @@ struct Dims {
   static constexpr int FC = (Nfp + 3) / 4;    // 4-column chunks per face of LIFT
   static constexpr int OPS = (3 * NR * NK + NR * 4 * FC) * 64;   // operator fragment floats
   static constexpr int TABW = (4 * 4 * 6 * Nfp + 3) / 4;          // face-node map, in 32-bit words
-  static constexpr int FS = trace_face_stride(Nfp);               // trace row: face stride,
-  static constexpr int TRC = 4 * FS;                              // component stride,
-  static constexpr int TRS = 2 * TRC;                             // element stride (floats)
+  static constexpr int FS = trace_face_stride(Nfp);               // trace row: run length,
+  static constexpr int TRC = FS;                                  // component stride (p, then n.v),
+  static constexpr int TRF = 2 * FS;                              // face stride,
+  static constexpr int TRS = 4 * TRF;                             // element stride (floats)
 };
 
 // index of field c, node n of tile element e in an LDS copy of a tile's state (quad layout)
@@ -457,7 +458,7 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
         const int fi = sel4(g, T.fidx[min(16 * rt + i, Np - 1)][f], T.fidx[min(16 * rt + 4 + i, Np - 1)][f],
                             T.fidx[min(16 * rt + 8 + i, Np - 1)][f], T.fidx[min(16 * rt + 12 + i, Np - 1)][f]);
         if (fi >= 0) {
-          const int64_t r0 = (int64_t)k * TRS + f * FS + fi;
+          const int64_t r0 = (int64_t)k * TRS + f * Dims<N>::TRF + fi;
           const int64_t r1 = r0 + TRC;
           if constexpr (!TRQ) {
             trw[r0] = qn[0];
@@ -489,8 +490,8 @@ __device__ __forceinline__ void tile_traces(const StepArgs &a, const SlotArgs &s
   const float nx = g == 0 ? nfx[0] : (g == 1 ? nfx[1] : (g == 2 ? nfx[2] : nfx[3]));
   const float ny = g == 0 ? nfy[0] : (g == 1 ? nfy[1] : (g == 2 ? nfy[2] : nfy[3]));
   const float nz = g == 0 ? nfz[0] : (g == 1 ? nfz[1] : (g == 2 ? nfz[2] : nfz[3]));
-  float *trw = sl.tr + ((m + 1) & 1) * (int64_t)TRS * K + k * TRS + g * FS;
-  float *trm = sl.tr + (int64_t)2 * TRS * K + k * TRS + g * FS;
+  float *trw = sl.tr + ((m + 1) & 1) * (int64_t)TRS * K + k * TRS + g * Dims<N>::TRF;
+  float *trm = sl.tr + (int64_t)2 * TRS * K + k * TRS + g * Dims<N>::TRF;
 #pragma unroll
   for (int j = 0; j < FS / 4; ++j) {
     float p[4], v[4], pm[4], vm[4];
@@ -728,7 +729,7 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
           run = replay_row<N>(a, sl, lev_t, m_t, code) + 4 * g;
           run2 = run + Dm::FS;
         } else {
-          run = trp + (int64_t)nb * Dm::TRS + f2 * Dm::FS + 4 * g;
+          run = trp + (int64_t)nb * Dm::TRS + f2 * Dm::TRF + 4 * g;
           run2 = run + Dm::TRC;
         }
         lds_copy16(run, ln + 4 * (2 * f + 0) * 16 * Dm::FS);
@@ -1250,7 +1251,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       const bool inner = fc.nb >= 0;
       // the face-node map in LDS: fc.tab points into the global copy at the same offset
       const int8_t *tab = stab + (fc.tab - a.nbr_index);
-      const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::FS +
+      const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::TRF +
                          tab[inner ? min(4 * cc + g, Nfp - 1) : 0];
       p_ = inner ? nbt[0] : 0.0f;
       v_ = inner ? nbt[Dm::TRC] : 0.0f;
@@ -1316,7 +1317,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
             const bool sv = 16 * cc + 12 + v < Nfp || s < Nfp;
             const int node = sel4(g, T.fmask[f][min(16 * cc + v, Nfp - 1)], T.fmask[f][min(16 * cc + 4 + v, Nfp - 1)],
                                   T.fmask[f][min(16 * cc + 8 + v, Nfp - 1)], T.fmask[f][min(16 * cc + 12 + v, Nfp - 1)]);
-            const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::FS +
+            const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::TRF +
                                tab[inner ? min(s, Nfp - 1) : 0];
             float tps = inner ? nbt[0] : 0.0f, tvs = inner ? nbt[Dm::TRC] : 0.0f;
             if constexpr (REPLAY) {
@@ -1413,8 +1414,8 @@ __global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) 
       const float vx = a.q[qix(node_quads(Np), 1, node, k)];
       const float vy = a.q[qix(node_quads(Np), 2, node, k)];
       const float vz = a.q[qix(node_quads(Np), 3, node, k)];
-      tr[(int64_t)k * TRS + f * FS + i] = p;
-      tr[(int64_t)k * TRS + TRC + f * FS + i] = nx * vx + ny * vy + nz * vz;
+      tr[(int64_t)k * TRS + f * Dims<N>::TRF + i] = p;
+      tr[(int64_t)k * TRS + f * Dims<N>::TRF + TRC + i] = nx * vx + ny * vy + nz * vz;
     }
   }
 }
@@ -1460,8 +1461,8 @@ __global__ __launch_bounds__(256) void bnd_record_kernel(const BndRecArgs a) {
   const int f = sf & 3;
   const int lev = level_of(a.lev_begin, a.L, k);
   const int64_t j = (a.tau >> (a.L - lev)) + 1;   // own step reached by the launch at tau
-  const float4 v = *reinterpret_cast<const float4 *>(a.tr + (j & 1) * (int64_t)TRS * a.Ktot + k * TRS + comp * TRC +
-                                                     f * FS + 4 * c);
+  const float4 v = *reinterpret_cast<const float4 *>(a.tr + (j & 1) * (int64_t)TRS * a.Ktot + k * TRS +
+                                                     f * Dims<N>::TRF + comp * TRC + 4 * c);
   const float sg = comp ? -1.0f : 1.0f;
   const int64_t b = i - a.bnd_begin[lev - 1];
   float *dst = a.rec + a.bnd_off[lev - 1] + (j * a.bnd_cnt[lev - 1] + b) * (2 * FS) + comp * FS + 4 * c;

@@ -6,8 +6,10 @@
 // tile is 64 contiguous bytes and a tile's R rows are one contiguous block.
 //   q     quad layout, qix()       p, vx, vy, vz
 //   ring  [3] x quad layout        AB3 right-hand-side history, slot = own step index mod 3
-//   tr    [3][Ktot][2][4][FS]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step;
-//                                  face f's Nfp values start at f*FS, FS = Nfp rounded up to 4
+//   tr    [3][Ktot][4][2][FS]      traces p and n.v: slot 0/1 = own step parity, slot 2 = mid step;
+//                                  face f's p run starts at 2 f FS and its n.v run at (2 f + 1) FS,
+//                                  FS = Nfp rounded up to 4 (one face's two runs are one 128-byte
+//                                  line at N = 4, so a neighbour's read of a face fetches no other)
 //   geo   [kGeo rows]              rx ry rz sx sy sz tx ty tz, rho c^2, 1/rho, Z, tau_p[4], tau_v[4]
 //   nbr   [4 rows]                 neighbour position, or -(boundary type) on a boundary face
 //   ncode [4 rows]                 neighbour face | vertex permutation << 2 | neighbour level << 5
@@ -57,7 +59,7 @@ __host__ __device__ constexpr int64_t tix(int64_t R, int64_t r, int64_t k) { ret
 
 // face stride of a trace row: Nfp rounded up to a multiple of 4 floats (16-byte aligned runs)
 __host__ __device__ constexpr int trace_face_stride(int Nfp) { return (Nfp + 3) & ~3; }
-// floats of one element's trace row (two components, four faces)
+// floats of one element's trace row (four faces, two components)
 __host__ __device__ constexpr int trace_row(int Nfp) { return 8 * trace_face_stride(Nfp); }
 
 // Per-shot ("slot") part of a step launch: several shots on the same mesh, at the same phase of
