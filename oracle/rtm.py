@@ -73,10 +73,12 @@ class Shot:
 
     # ---------------------------------------------------------------- forward
     def forward(self, condition=COND_CHARACTERISTIC, up=(0.0, 0.0, 1.0), keep=True, record_boundary=False,
-                q0=None):
+                q0=None, snap_every=0, progress=None):
         """Run S; return traces (n_rec, n_global+1); keep per element-step q-_S and r-_S.
 
         q0: state at t = 0 (zero AB3 history); default: at rest.
+        snap_every: also keep the state after every snap_every global steps (self.snaps).
+        progress(g): called after every global step (long runs report their steps).
 
         record_boundary: also save the boundary traces after every own step of the elements that
         have a boundary face (self.bnd_rec: (n_bnd, J+1, 4, Nfp, 2), row j = own step j, row 0 the
@@ -120,17 +122,22 @@ class Shot:
             self.bnd_rec[:, 0] = op.traces(st.q, np.flatnonzero(b))
         tr = np.zeros((self.rec_elem.size, self.n_global + 1))
         tr[:, 0] = np.einsum("rn,rn->r", self.rec_l, st.q[self.rec_elem, 0])
+        self.snaps = []
         for g in range(self.n_global):
             st.global_step()
             tr[:, g + 1] = np.einsum("rn,rn->r", self.rec_l, st.q[self.rec_elem, 0])
             if record_boundary and g + 1 >= self.n_global - 2:
                 self.q_end[g + 1] = st.q.copy()
+            if snap_every and (g + 1) % snap_every == 0:
+                self.snaps.append(st.q.copy())
+            if progress is not None:
+                progress(g + 1)
         self.S_final = st.q.copy()
         return tr
 
     # ---------------------------------------------------------------- backward + image
     def adjoint(self, data: np.ndarray, condition=COND_CHARACTERISTIC, up=(0.0, 0.0, 1.0),
-                g_image_start: int = 0, quadrature: bool = False, rule: str = "exact"):
+                g_image_start: int = 0, quadrature: bool = False, rule: str = "exact", progress=None):
         """Run R backward over [t_i, t_f] with the data injected; return the FP64 image (K, Np).
 
         rule "exact": the dense-output integral (quadrature=True: by Gauss-Legendre quadrature);
@@ -200,6 +207,8 @@ class Shot:
         st = MRAB(op, self.lev, self.L, self.dt_local, reversed_time=True, src=src, on_eval=on_eval)
         for g in range(self.n_global - g_image_start):
             st.global_step()
+            if progress is not None:
+                progress(g + 1)
         self.R_final = st.q.copy()
         if rule == "trapezoid":
             # S at the end of its last step is the final state; R at the end of its last step is R_final
