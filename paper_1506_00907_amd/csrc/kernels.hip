@@ -1085,7 +1085,9 @@ __global__ __launch_bounds__(256) void step_kernel_dma(const StepArgs a) {
 // leave room in LDS for one tile per wavefront, but not for the neighbour runs and the history:
 // each wavefront's state and geometry tiles come by LDS copies, issued for the next tile as soon
 // as the update has read the state; neighbour traces and the older rhs are read per lane.
-template <int N, int MODE, bool OPS_LDS, int PREC>
+// OPS_LDS: where the operator fragments are read from: 0 through the caches, 1 all of them from LDS,
+// 2 the lift fragments from LDS and the volume fragments through the caches
+template <int N, int MODE, int OPS_LDS, int PREC>
 __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   constexpr Tab<N> T{};
   using Dm = Dims<N>;
@@ -1101,14 +1103,17 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   constexpr bool REPLAY = MODE == MODE_REPLAY_SEG || MODE == MODE_RHS_REPLAY;
   constexpr int BM = base_mode(MODE);
   constexpr int VU = LEAN ? 1 : 2;
-  extern __shared__ __align__(16) float sdyn[];   // [operators if OPS_LDS][4 wavefronts][QW + GW]
+  // floats of the volume fragments, and of the operators held in LDS
+  constexpr int DW = PREC ? 3 * NR * DB::NK * 64 * 4 : 3 * NR * NK * 64;
+  constexpr int LDSOPS = OPS_LDS == 1 ? OPSW : (OPS_LDS == 2 ? OPSW - DW : 0);
+  extern __shared__ __align__(16) float sdyn[];   // [operators in LDS][4 wavefronts][QW + GW]
   __shared__ __align__(16) uint32_t stabw[Dm::TABW];   // face-node map [4][4][6][Nfp]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = lane & 15, g = lane >> 4;
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
   const SlotArgs &sl = a.slot[blockIdx.y];
-  float *const q_t = sdyn + (OPS_LDS ? OPSW : 0) + wave * (QW + GW);
+  float *const q_t = sdyn + LDSOPS + wave * (QW + GW);
   float *const g_t = q_t + QW;
   const uint32_t lq = __builtin_amdgcn_readfirstlane(lds_addr(q_t));
   const uint32_t lg = lq + 4 * QW;
@@ -1124,9 +1129,14 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   };
   if (tile < ntiles) issue(tile);
   const float *ops = PREC ? reinterpret_cast<const float *>(a.ops_bf16) : a.ops;
-  if constexpr (OPS_LDS) {
+  const float *lift = ops + DW;
+  if constexpr (OPS_LDS == 1) {
     stage_dma<4 * OPSW>(ops, sdyn, wave, lane);
     ops = sdyn;
+    lift = sdyn + DW;
+  } else if constexpr (OPS_LDS == 2) {
+    stage_dma<4 * (OPSW - DW)>(lift, sdyn, wave, lane);
+    lift = sdyn;
   }
   stage_dma<4 * Dm::TABW>(a.nbr_index, stabw, wave, lane);
   const int8_t *stab = reinterpret_cast<const int8_t *>(stabw);
@@ -1156,9 +1166,9 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     int opaque0;
     asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
     const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
-    const float *__restrict__ fL = ops + opaque0 + 3 * NR * NK * 64;    // [NR][4*FC][64]
+    const float *__restrict__ fL = lift + opaque0;                      // [NR][4*FC][64]
     const uint4 *__restrict__ bD = reinterpret_cast<const uint4 *>(ops) + opaque0;          // split-BF16
-    const uint4 *__restrict__ bL = bD + 3 * NR * DB::NK * 64;
+    const uint4 *__restrict__ bL = reinterpret_cast<const uint4 *>(lift) + opaque0;
     const int flag = sl.eflag[k];
     const int lev = level_of(a.lev_begin, a.L, tile * 16);   // uniform over the tile
     const int sh = a.L - lev;
@@ -1575,6 +1585,9 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
     constexpr size_t map = (size_t)4 * Dims<N>::TABW;
     constexpr size_t ops32 = (size_t)Dims<N>::OPS * sizeof(float);
     constexpr size_t opsb = (size_t)DimsB<N>::OPS_U4 * sizeof(uint4);
+    // the lift fragments alone (when the volume fragments do not fit beside the tiles)
+    constexpr size_t lift32 = ops32 - (size_t)3 * Dims<N>::NR * Dims<N>::NK * 64 * sizeof(float);
+    constexpr size_t liftb = opsb - (size_t)3 * Dims<N>::NR * DimsB<N>::NK * 64 * sizeof(uint4);
     const dim3 grid1((unsigned)std::max<int64_t>(1, std::min(groups, a.max_groups > 0 ? a.max_groups : device_cus())),
                      (unsigned)a.nslots), block(256);
     auto go = [&](auto kern, size_t lds) -> hipError_t {
@@ -1584,11 +1597,13 @@ static hipError_t launch_step_mode(const StepArgs &a, hipStream_t st) {
       return hipGetLastError();
     };
     if (a.precision == 1) {
-      if constexpr (opsb + tiles + map <= 160 * 1024) return go(step_kernel_lowreg<N, MODE, true, 1>, opsb + tiles);
-      else return go(step_kernel_lowreg<N, MODE, false, 1>, tiles);
+      if constexpr (opsb + tiles + map <= 160 * 1024) return go(step_kernel_lowreg<N, MODE, 1, 1>, opsb + tiles);
+      else if constexpr (liftb + tiles + map <= 160 * 1024) return go(step_kernel_lowreg<N, MODE, 2, 1>, liftb + tiles);
+      else return go(step_kernel_lowreg<N, MODE, 0, 1>, tiles);
     }
-    if constexpr (ops32 + tiles + map <= 160 * 1024) return go(step_kernel_lowreg<N, MODE, true, 0>, ops32 + tiles);
-    else return go(step_kernel_lowreg<N, MODE, false, 0>, tiles);
+    if constexpr (ops32 + tiles + map <= 160 * 1024) return go(step_kernel_lowreg<N, MODE, 1, 0>, ops32 + tiles);
+    else if constexpr (lift32 + tiles + map <= 160 * 1024) return go(step_kernel_lowreg<N, MODE, 2, 0>, lift32 + tiles);
+    else return go(step_kernel_lowreg<N, MODE, 0, 0>, tiles);
   } else {
     // one work-group per CU (its static LDS fills the CU); each loops over tiles.  A launch with
     // fewer than two tiles per wavefront of a full grid takes a smaller grid with two tiles per
