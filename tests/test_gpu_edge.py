@@ -2,7 +2,9 @@
 
 - a mesh of one tetrahedron (a single padded tile, every face a boundary, given with negative
   orientation so the library re-orients it), N = 1..6, both time directions;
-- the shortest shots: one and two global steps, with a checkpoint interval longer than the run;
+- the shortest shots: one and two global steps, with a checkpoint interval longer than the run,
+  and with boundary-trace replay (whose start history then reaches back before t = 0);
+- a one-tetrahedron shot with boundary-trace replay (every face replayed), N = 1..6;
 - a shot without receivers (no traces, a zero image, the same source field as with receivers);
 - source and receiver points outside the mesh (reported, nothing launched).
 """
@@ -44,8 +46,8 @@ def test_single_tetrahedron_rhs(N, reversed_time):
     assert rel(got.cpu().numpy(), ref) < 2e-6
 
 
-@pytest.mark.parametrize("ng,ckpt", [(1, 0), (1, 5), (2, 5)])
-def test_shortest_shots_image(ng, ckpt):
+@pytest.mark.parametrize("ng,ckpt,storage", [(1, 0, 0), (1, 5, 0), (2, 5, 0), (1, 0, 1), (2, 0, 1), (3, 0, 1)])
+def test_shortest_shots_image(ng, ckpt, storage):
     from paper_1506_00907_amd import dgrtm
     name = "two_layer_small:6:6:4:2"
     mm, rho, c, N = I.config_mesh(name)
@@ -56,19 +58,57 @@ def test_shortest_shots_image(ng, ckpt):
     spec = I.rtm_shot(src_xy=(0.75, 0.75), n_rec=4)
     spec.t_peak = 0.002
     shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=ng * dtl * 2 ** (L - 1), src=spec.src, f_peak=spec.f_peak,
-                                         t_peak=spec.t_peak, rec=spec.rec, ckpt_interval=ckpt))
+                                         t_peak=spec.t_peak, rec=spec.rec, ckpt_interval=ckpt, storage=storage))
     assert shot.n_global == ng
     tr = shot.forward()
     assert tr.shape == (16, ng + 1)
     shot.adjoint(tr, condition=dgrtm.IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start=0)
     img = shot.image().cpu().numpy()
     osh = oracle_shot(op, lev, L, dtl, ng, spec)
-    tr_ref = osh.forward(condition=COND_CHARACTERISTIC)
+    tr_ref = osh.forward(condition=COND_CHARACTERISTIC, record_boundary=bool(storage))
     assert np.abs(tr_ref[:, -1]).max() > 0
     assert rel(tr.cpu().numpy(), tr_ref) < 1e-5
-    img_ref = osh.adjoint(tr.cpu().numpy().astype(np.float64), condition=COND_CHARACTERISTIC, g_image_start=0)
+    run = osh.adjoint_replay if storage else osh.adjoint
+    img_ref = run(tr.cpu().numpy().astype(np.float64), condition=COND_CHARACTERISTIC, g_image_start=0)
     assert np.abs(img_ref).max() > 0
     assert rel(img, img_ref) < 1e-4
+    if storage:
+        assert rel(shot.get_state(dgrtm.SOURCE_FIELD).cpu().numpy(), osh.S_back) < 1e-5
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6])
+def test_single_tetrahedron_replay_shot(N):
+    """One tetrahedron with every face a boundary (rigid, transparent, free): the backward source
+    run takes the exterior state of all four faces from the record."""
+    from paper_1506_00907_amd import dgrtm
+    verts = np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.0], [0.2, 0.9, 0.1], [0.1, 0.2, 1.1]])
+    etov = np.array([[0, 2, 1, 3]], dtype=np.int64)
+    bc = np.array([[BC_RIGID, BC_TRANSPARENT, BC_FREE, BC_TRANSPARENT]], dtype=np.int8)
+    rho, c = np.array([1.7]), np.array([2.3])
+    lm = dgrtm.Mesh(N, verts, etov, face_bc=bc).set_model(rho, c, n_levels_max=3).bind("cuda")
+    src = np.array([0.3, 0.3, 0.3])
+    rec = np.array([[0.25, 0.3, 0.35]])
+    ng = 12
+    shot = dgrtm.Shot(lm, dgrtm.ShotSpec(t_final=ng * lm.dt_local, src=src, f_peak=15.0, t_peak=2 * lm.dt_local,
+                                         rec=rec, storage=dgrtm.STORE_BOUNDARY))
+    tr = shot.forward()
+    shot.adjoint(tr, condition=dgrtm.IMAGE_CHARACTERISTIC, up=(0.0, 0.0, 1.0), g_image_start=0)
+    img = shot.image().cpu().numpy()
+    om = OMesh(get_ref(N), verts, etov, face_bc=bc)
+    op = Operator(om, rho, c)
+    lev, L, dtl = lts_levels(local_dt(om.verts, om.etov, c, N), om.EToE, 3)
+    from tests.oracle_cases import oracle_shot as osf
+
+    class Spec:
+        pass
+    sp = Spec()
+    sp.src, sp.f_peak, sp.t_peak, sp.rec = src, 15.0, 2 * lm.dt_local, rec
+    osh = osf(op, lev, L, dtl, ng, sp)
+    tr_ref = osh.forward(condition=COND_CHARACTERISTIC, record_boundary=True)
+    assert rel(tr.cpu().numpy(), tr_ref) < 1e-5
+    img_ref = osh.adjoint_replay(tr.cpu().numpy().astype(np.float64), condition=COND_CHARACTERISTIC)
+    assert rel(img, img_ref) < 1e-4
+    assert rel(shot.get_state(dgrtm.SOURCE_FIELD).cpu().numpy(), osh.S_back) < 1e-5
 
 
 def test_shot_without_receivers():
