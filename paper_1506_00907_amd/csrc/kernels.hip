@@ -218,7 +218,7 @@ __device__ __forceinline__ void seg_offsets(const StepArgs &a, int64_t C, int Np
 // Without HLDS / TR2 the older rhs are read, and the new rhs and state written, as one 16-byte
 // access per field and node quad.
 template <int N, int MODE, bool QLDS = false, bool HLDS = false, bool TR2 = false, bool PRE = false,
-          bool TRQ = false>
+          bool TRQ = false, bool PF = false>
 __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl, int64_t k, int g, int lev, int sh,
                                           int64_t m, int flag, float *sq, int e,
                                           float Z, const float (&nfx)[4], const float (&nfy)[4], const float (&nfz)[4],
@@ -331,9 +331,24 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
   }
   const double dtd = a.dt_local * (double)(1LL << sh);
 
+  // the rhs history of the lane's node quad in row tile rt (rows past the last quad hold no nodes)
+  float4 hq1[NR][4], hq2[NR][4];
+  auto load_hist = [&](int rt) {
+    const int qd = 4 * rt + g;
+    const bool qok = 4 * rt + 3 < NQ4 || qd < NQ4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t iq = qix(NQ4, c, 4 * (qok ? qd : 0), k);
+      hq1[rt][c] = *reinterpret_cast<const float4 *>(R1 + iq);
+      hq2[rt][c] = *reinterpret_cast<const float4 *>(R2 + iq);
+    }
+  };
+  if constexpr (PF && !HLDS) load_hist(0);
   // Row tile by row tile: every load of the tile (rhs history, q, segment data, image) is issued
   // before any store, so the loads of one row tile are in flight together (stores to the ring could
-  // otherwise alias later ring loads and serialise every load behind the previous store).
+  // otherwise alias later ring loads and serialise every load behind the previous store).  With PF
+  // the next row tile's history loads are issued before this row tile's work, so that their
+  // latency overlaps it.
 #pragma unroll
   for (int rt = 0; rt < NR; ++rt) {
     float h1[4][4], h2[4][4], qo[4][4];
@@ -343,11 +358,16 @@ __device__ __forceinline__ void tile_tail(const StepArgs &a, const SlotArgs &sl,
     const int qd = 4 * rt + g;
     const bool qok = 4 * rt + 3 < NQ4 || qd < NQ4;
     if constexpr (!HLDS) {
+      if constexpr (PF) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (rt + 1 < NR) load_hist(rt + 1);
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        load_hist(rt);
+      }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int64_t iq = qix(NQ4, c, 4 * (qok ? qd : 0), k);
-        const float4 a1 = *reinterpret_cast<const float4 *>(R1 + iq);
-        const float4 a2 = *reinterpret_cast<const float4 *>(R2 + iq);
+        const float4 a1 = hq1[rt][c], a2 = hq2[rt][c];
         h1[0][c] = qok ? a1.x : 0.f; h1[1][c] = qok ? a1.y : 0.f; h1[2][c] = qok ? a1.z : 0.f; h1[3][c] = qok ? a1.w : 0.f;
         h2[0][c] = qok ? a2.x : 0.f; h2[1][c] = qok ? a2.y : 0.f; h2[2][c] = qok ? a2.z : 0.f; h2[3][c] = qok ? a2.w : 0.f;
       }
@@ -1097,12 +1117,12 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   // operator fragment floats: FP32 [3][NR][NK][64] + [NR][4 FC][64], split-BF16 the same in uint4
   constexpr int OPSW = PREC ? DB::OPS_U4 * 4 : Dm::OPS;
   constexpr int QW = DD::QW, GW = DD::GW;
-  // N = 6 has no registers to spare: one volume chunk at a time, neighbour traces read per chunk
-  constexpr bool LEAN = N >= 6;
   // the replay modes are the record and rhs-only modes with replayed boundary faces
   constexpr bool REPLAY = MODE == MODE_REPLAY_SEG || MODE == MODE_RHS_REPLAY;
   constexpr int BM = base_mode(MODE);
-  constexpr int VU = LEAN ? 1 : 2;
+  // volume chunks per unrolled loop step where a chunk's fragments are read in its own step
+  // (N = 6 has no registers to spare for two)
+  constexpr int VU = N >= 6 ? 1 : 2;
   // floats of the volume fragments, and of the operators held in LDS
   constexpr int DW = PREC ? 3 * NR * DB::NK * 64 * 4 : 3 * NR * NK * 64;
   constexpr int LDSOPS = OPS_LDS == 1 ? OPSW : (OPS_LDS == 2 ? OPSW - DW : 0);
@@ -1186,8 +1206,8 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
 #pragma unroll
     for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
     if constexpr (PREC == 0) {
-#pragma unroll VU
-      for (int c = 0; c < NK; ++c) {
+      // the products of one 4-column chunk, A fragments given
+      auto vchunk = [&](int c, const float (&fa)[3][NR]) {
         const int mm = 4 * c + g;
         const bool ok = mm < Np;
         const int mr = ok ? mm : 0;
@@ -1200,15 +1220,44 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         const float Ut = tx * vx + ty * vy + tz * vz;
 #pragma unroll
         for (int rt = 0; rt < NR; ++rt) {
-          const float ar = fD[((0 * NR + rt) * NK + c) * 64 + lane];
-          const float as = fD[((1 * NR + rt) * NK + c) * 64 + lane];
-          const float at = fD[((2 * NR + rt) * NK + c) * 64 + lane];
-          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, Ur, cp[rt], 0, 0, 0);
-          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, Us, cp[rt], 0, 0, 0);
-          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, Ut, cp[rt], 0, 0, 0);
-          w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, p, w0[rt], 0, 0, 0);
-          w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, p, w1[rt], 0, 0, 0);
-          w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(at, p, w2[rt], 0, 0, 0);
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[0][rt], Ur, cp[rt], 0, 0, 0);
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[1][rt], Us, cp[rt], 0, 0, 0);
+          cp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[2][rt], Ut, cp[rt], 0, 0, 0);
+          w0[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[0][rt], p, w0[rt], 0, 0, 0);
+          w1[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[1][rt], p, w1[rt], 0, 0, 0);
+          w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[2][rt], p, w2[rt], 0, 0, 0);
+        }
+      };
+      auto vload = [&](int c, float (&fa)[3][NR]) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int rt = 0; rt < NR; ++rt) fa[j][rt] = fD[((j * NR + rt) * NK + c) * 64 + lane];
+      };
+      float fa[3][NR], fb[3][NR];
+      if constexpr (OPS_LDS != 1) {
+        // Fragments read through the caches: two register buffers, the next chunk's loads in
+        // flight while a chunk's products run.  The loads past the last chunk re-read it
+        // (unconditional loads keep the waits exact), and scheduling barriers keep each chunk's
+        // loads in one batch, so that the wait before a chunk's products leaves the other
+        // buffer's loads in flight.
+        vload(0, fa);
+        for (int c = 0; c < NK; c += 2) {
+          __builtin_amdgcn_sched_barrier(0);
+          vload(min(c + 1, NK - 1), fb);
+          __builtin_amdgcn_sched_barrier(0);
+          vchunk(c, fa);
+          __builtin_amdgcn_sched_barrier(0);
+          vload(min(c + 2, NK - 1), fa);
+          __builtin_amdgcn_sched_barrier(0);
+          if (c + 1 < NK) vchunk(c + 1, fb);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+#pragma unroll VU
+        for (int c = 0; c < NK; ++c) {
+          vload(c, fa);
+          vchunk(c, fa);
         }
       }
     } else {
@@ -1256,7 +1305,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     FaceCtx fcs[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) fcs[f] = face_ctx_of<N>(a, sl, f, gg, nbv[f], cdv[f]);
-    // the neighbour's traces at this lane's face nodes: all faces in one batch unless LEAN
+    // the neighbour's traces at this lane's face nodes (the FP32 form loads all faces in one batch)
     auto nbtrace = [&](const FaceCtx &fc, int cc, float &p_, float &v_) {
       const bool inner = fc.nb >= 0;
       // the face-node map in LDS: fc.tab points into the global copy at the same offset
@@ -1275,7 +1324,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       }
     };
     float tpa[4][FC], tva[4][FC];
-    if constexpr (!LEAN && PREC == 0) {
+    if constexpr (PREC == 0) {
 #pragma unroll
       for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -1294,6 +1343,9 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
       if constexpr (PREC == 0) {
+        // the face's penalties first, then its products (the fragment reads run ahead of the
+        // products instead of waiting behind each chunk's penalty arithmetic)
+        float mPp[FC], Pv[FC];
 #pragma unroll
         for (int cc = 0; cc < FC; ++cc) {
           const bool sv = 4 * cc + 3 < Nfp || 4 * cc + g < Nfp;   // face node 4 cc + g exists
@@ -1302,19 +1354,20 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
           const float pm = q_t[lqix<N>(0, node, e)];
           const float nvm = fc.nx * q_t[lqix<N>(1, node, e)] + fc.ny * q_t[lqix<N>(2, node, e)] +
                             fc.nz * q_t[lqix<N>(3, node, e)];
-          if constexpr (LEAN) nbtrace(fc, cc, tp[cc], tv[cc]);
           const float pp = cP * pm + tp[cc];
           const float nvp = -(cP * nvm + tv[cc]);
           const float dp = pp - pm, dnv = nvp - nvm;
-          const float mPp = sv ? -0.5f * rc2 * (dnv - fc.taup * dp) * fc.Fs : 0.0f;
-          const float Pv = sv ? 0.5f * irho * (dp - fc.tauv * dnv) * fc.Fs : 0.0f;
+          mPp[cc] = sv ? -0.5f * rc2 * (dnv - fc.taup * dp) * fc.Fs : 0.0f;
+          Pv[cc] = sv ? 0.5f * irho * (dp - fc.tauv * dnv) * fc.Fs : 0.0f;
+        }
+#pragma unroll
+        for (int cc = 0; cc < FC; ++cc)
 #pragma unroll
           for (int rt = 0; rt < NR; ++rt) {
             const float al = fL[(rt * 4 * FC + f * FC + cc) * 64 + lane];
-            rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp, rp[rt], 0, 0, 0);
-            G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv, G[rt], 0, 0, 0);
+            rp[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, mPp[cc], rp[rt], 0, 0, 0);
+            G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv[cc], G[rt], 0, 0, 0);
           }
-        }
       } else {
         const bool inner = fc.nb >= 0;
         const int8_t *tab = stab + (fc.tab - a.nbr_index);
@@ -1367,7 +1420,10 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    tile_tail<N, BM, true, false, false, false, BM != MODE_RHS_ONLY>(a, sl, k, g, lev, sh, m, flag, q_t, e,
+    // the update prefetches the next row tile's rhs history where that costs no spills (measured:
+    // the forward step at N = 5 and 6, and the segment-record step at N = 5)
+    constexpr bool PF = BM == MODE_PLAIN || (N == 5 && BM == MODE_RECORD_SEG);
+    tile_tail<N, BM, true, false, false, false, BM != MODE_RHS_ONLY, PF>(a, sl, k, g, lev, sh, m, flag, q_t, e,
                                                                     gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
     // own-step traces of the new state (now in the state tile); the half-step ones went out per lane
     if constexpr (BM != MODE_RHS_ONLY) tile_traces<N, false>(a, sl, k, g, e, m, flag, q_t, nullptr, nfx, nfy, nfz);
