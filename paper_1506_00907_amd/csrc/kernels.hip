@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   extern __shared__ __align__(16) float sdyn[];   // [operators in LDS][4 wavefronts][QW + GW]
   __shared__ __align__(16) uint32_t stabw[Dm::TABW];   // face-node map [4][4][6][Nfp]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int e = lane & 15, g = lane >> 4;
+  const int e = lane & 15, g_lane = lane >> 4;
   const int64_t K = a.Ktot;
   const int64_t ntiles = a.k_end >> 4;
   const SlotArgs &sl = a.slot[blockIdx.y];
@@ -1171,6 +1171,14 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     __builtin_amdgcn_sched_barrier(0);
     DGRTM_WAIT_VM(0);
     __builtin_amdgcn_sched_barrier(0);
+    // An opaque zero keeps the operator-fragment reads inside the tile loop (hoisting them out would
+    // pin every fragment in registers for the whole kernel).  At N = 6 outside the forward step it
+    // also keeps there the lane's face-node and node-quad selections, which depend on its row group
+    // g: hoisted, they would hold about a hundred registers through the loop and make the update
+    // spill; recomputed, they cost a few hundred VALU instructions per tile.
+    int opaque0;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
+    const int g = (N >= 6 && BM != MODE_PLAIN) ? g_lane + opaque0 : g_lane;
     const int64_t k = tile * 16 + e;
     uint32_t vnn = 0u;   // the tile after the next (counter value), read at the end of this tile
     if (dyn && nxt < ntiles && lane == 0) vnn = atomicAdd(ctr, 1u);
@@ -1181,10 +1189,6 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       nbv[f] = a.nbr[tix(4, f, k)];
       cdv[f] = a.ncode[tix(4, f, k)];
     }
-    // an opaque zero keeps the operator-fragment reads inside the tile loop (hoisting them out
-    // would pin every fragment in registers for the whole kernel)
-    int opaque0;
-    asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
     const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
     const float *__restrict__ fL = lift + opaque0;                      // [NR][4*FC][64]
     const uint4 *__restrict__ bD = reinterpret_cast<const uint4 *>(ops) + opaque0;          // split-BF16
@@ -1420,9 +1424,9 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    // the update prefetches the next row tile's rhs history where that costs no spills (measured:
-    // the forward step at N = 5 and 6, and the segment-record step at N = 5)
-    constexpr bool PF = BM == MODE_PLAIN || (N == 5 && BM == MODE_RECORD_SEG);
+    // the update prefetches the next row tile's rhs history where that costs no spills and pays
+    // (measured: every step at N = 6, the forward and segment-record steps at N = 5)
+    constexpr bool PF = BM == MODE_PLAIN || (N == 5 && BM == MODE_RECORD_SEG) || N >= 6;
     tile_tail<N, BM, true, false, false, false, BM != MODE_RHS_ONLY, PF>(a, sl, k, g, lev, sh, m, flag, q_t, e,
                                                                     gg[11], nfx, nfy, nfz, rp, rvx, rvy, rvz);
     // own-step traces of the new state (now in the state tile); the half-step ones went out per lane
