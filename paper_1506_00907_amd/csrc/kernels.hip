@@ -1210,15 +1210,17 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
 #pragma unroll
     for (int rt = 0; rt < NR; ++rt) cp[rt] = w0[rt] = w1[rt] = w2[rt] = v4f{0.f, 0.f, 0.f, 0.f};
     if constexpr (PREC == 0) {
-      // the products of one 4-column chunk, A fragments given
-      auto vchunk = [&](int c, const float (&fa)[3][NR]) {
+      // the B operands of one 4-column chunk: node 4 c + g of the lane's element, four fields
+      auto bload = [&](int c, float (&b)[4]) {
         const int mm = 4 * c + g;
         const bool ok = mm < Np;
         const int mr = ok ? mm : 0;
-        const float p = ok ? q_t[lqix<N>(0, mr, e)] : 0.f;
-        const float vx = ok ? q_t[lqix<N>(1, mr, e)] : 0.f;
-        const float vy = ok ? q_t[lqix<N>(2, mr, e)] : 0.f;
-        const float vz = ok ? q_t[lqix<N>(3, mr, e)] : 0.f;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) b[f] = ok ? q_t[lqix<N>(f, mr, e)] : 0.f;
+      };
+      // the products of one 4-column chunk, its B operands given
+      auto vchunkb = [&](const float (&b)[4], const float (&fa)[3][NR]) {
+        const float p = b[0], vx = b[1], vy = b[2], vz = b[3];
         const float Ur = rx * vx + ry * vy + rz * vz;
         const float Us = sx * vx + sy * vy + sz * vz;
         const float Ut = tx * vx + ty * vy + tz * vz;
@@ -1232,29 +1234,62 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
           w2[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[2][rt], p, w2[rt], 0, 0, 0);
         }
       };
+      // the products of one 4-column chunk, A fragments given
+      auto vchunk = [&](int c, const float (&fa)[3][NR]) {
+        float b[4];
+        bload(c, b);
+        vchunkb(b, fa);
+      };
       auto vload = [&](int c, float (&fa)[3][NR]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
           for (int rt = 0; rt < NR; ++rt) fa[j][rt] = fD[((j * NR + rt) * NK + c) * 64 + lane];
       };
-      float fa[3][NR], fb[3][NR];
+      float fa[3][NR];
       if constexpr (OPS_LDS != 1) {
-        // Fragments read through the caches: two register buffers, the next chunk's loads in
-        // flight while a chunk's products run.  The loads past the last chunk re-read it
-        // (unconditional loads keep the waits exact), and scheduling barriers keep each chunk's
-        // loads in one batch, so that the wait before a chunk's products leaves the other
-        // buffer's loads in flight.
-        vload(0, fa);
-        for (int c = 0; c < NK; c += 2) {
+        // Fragments read through the caches, two column chunks per 8-byte load (the paired copy
+        // after the lift fragments): two register buffers of chunk pairs, the next pair's loads in
+        // flight while a pair's products run.  The loads past the last pair re-read it
+        // (unconditional loads keep the waits exact), and scheduling barriers keep each pair's
+        // loads in one batch, so that the wait before a pair's products leaves the other buffer's
+        // loads in flight.
+        static_assert(N >= 6, "the paired volume fragments are built for N >= 6");
+        constexpr int NK2 = (NK + 1) / 2;
+        const float2 *__restrict__ fP = reinterpret_cast<const float2 *>(a.ops + Dm::OPS) + opaque0;
+        // a pair's A fragments and its B operands (from LDS) are loaded together, a pair ahead
+        auto pload = [&](int c2, float2 (&fp)[3][NR], float (&b)[2][4]) {
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int rt = 0; rt < NR; ++rt) fp[j][rt] = fP[((j * NR + rt) * NK2 + c2) * 64 + lane];
+          bload(2 * c2, b[0]);
+          bload(min(2 * c2 + 1, NK - 1), b[1]);
+        };
+        auto pchunks = [&](int c2, const float2 (&fp)[3][NR], const float (&b)[2][4]) {
+          float f0[3][NR], f1[3][NR];
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int rt = 0; rt < NR; ++rt) {
+              f0[j][rt] = fp[j][rt].x;
+              f1[j][rt] = fp[j][rt].y;
+            }
+          vchunkb(b[0], f0);
+          if (2 * c2 + 1 < NK) vchunkb(b[1], f1);
+        };
+        float2 pa[3][NR], pb[3][NR];
+        float ba[2][4], bb[2][4];
+        pload(0, pa, ba);
+        for (int c2 = 0; c2 < NK2; c2 += 2) {
           __builtin_amdgcn_sched_barrier(0);
-          vload(min(c + 1, NK - 1), fb);
+          pload(min(c2 + 1, NK2 - 1), pb, bb);
           __builtin_amdgcn_sched_barrier(0);
-          vchunk(c, fa);
+          pchunks(c2, pa, ba);
           __builtin_amdgcn_sched_barrier(0);
-          vload(min(c + 2, NK - 1), fa);
+          pload(min(c2 + 2, NK2 - 1), pa, ba);
           __builtin_amdgcn_sched_barrier(0);
-          if (c + 1 < NK) vchunk(c + 1, fb);
+          if (c2 + 1 < NK2) pchunks(c2 + 1, pb, bb);
         }
         __builtin_amdgcn_sched_barrier(0);
       } else {
@@ -1714,6 +1749,22 @@ void build_op_fragments(int N, const float *Dr, const float *Ds, const float *Dt
           const int row = 16 * rt + (l & 15), s = 4 * cc + (l >> 4);
           L[(rt * 4 * FC + f * FC + cc) * 64 + l] = (row < Np && s < Nfp) ? LIFT[row * F + f * Nfp + s] : 0.0f;
         }
+  if (N >= 6) {
+    // the volume fragments again, two column chunks per lane and 8-byte word: [3][NR][NK/2][64][2]
+    // (read through the caches, one load per operator and row tile gives two chunks' A operands)
+    const int NK2 = (NK + 1) / 2;
+    float *P = L + NR * 4 * FC * 64;
+    for (int j = 0; j < 3; ++j)
+      for (int rt = 0; rt < NR; ++rt)
+        for (int c2 = 0; c2 < NK2; ++c2)
+          for (int l = 0; l < 64; ++l)
+            for (int h = 0; h < 2; ++h) {
+              const int c = 2 * c2 + h;
+              const int row = 16 * rt + (l & 15), col = 4 * c + (l >> 4);
+              P[(((j * NR + rt) * NK2 + c2) * 64 + l) * 2 + h] =
+                  (c < NK && row < Np && col < Np) ? D[j][row * Np + col] : 0.0f;
+            }
+  }
 }
 
 static uint16_t host_bf16(float x) {
@@ -1781,7 +1832,8 @@ int64_t op_fragment_bf16_words(int N) {
 int64_t op_fragment_floats(int N) {
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
   const int NR = (Np + 15) / 16, NK = (Np + 3) / 4, FC = (Nfp + 3) / 4;
-  return (int64_t)(3 * NR * NK + NR * 4 * FC) * 64;
+  const int64_t paired = N >= 6 ? (int64_t)3 * NR * ((NK + 1) / 2) * 64 * 2 : 0;
+  return (int64_t)(3 * NR * NK + NR * 4 * FC) * 64 + paired;
 }
 
 hipError_t launch_step(int N, const StepArgs &a, hipStream_t st) {
