@@ -1172,13 +1172,14 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     DGRTM_WAIT_VM(0);
     __builtin_amdgcn_sched_barrier(0);
     // An opaque zero keeps the operator-fragment reads inside the tile loop (hoisting them out would
-    // pin every fragment in registers for the whole kernel).  At N = 6 outside the forward step it
-    // also keeps there the lane's face-node and node-quad selections, which depend on its row group
-    // g: hoisted, they would hold about a hundred registers through the loop and make the update
-    // spill; recomputed, they cost a few hundred VALU instructions per tile.
+    // pin every fragment in registers for the whole kernel).  At N = 6, outside the FP32 forward
+    // step, it also keeps there the lane's face-node and node-quad selections, which depend on its
+    // row group g: hoisted, they would hold about a hundred registers through the loop, which the
+    // update's history prefetch and the split-BF16 form's second fragment buffer need instead;
+    // recomputed, they cost a few hundred VALU instructions per tile.
     int opaque0;
     asm volatile("s_mov_b32 %0, 0" : "=s"(opaque0));
-    const int g = (N >= 6 && BM != MODE_PLAIN) ? g_lane + opaque0 : g_lane;
+    const int g = (N >= 6 && (BM != MODE_PLAIN || PREC == 1)) ? g_lane + opaque0 : g_lane;
     const int64_t k = tile * 16 + e;
     uint32_t vnn = 0u;   // the tile after the next (counter value), read at the end of this tile
     if (dyn && nxt < ntiles && lane == 0) vnn = atomicAdd(ctr, 1u);
@@ -1301,8 +1302,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       }
     } else {
       // lane (e, g) supplies B rows 16 c + 4 g .. + 3: node quad 4 c + g of each field
-#pragma unroll VU
-      for (int c = 0; c < DB::NK; ++c) {
+      auto bchunk = [&](int c, const uint4 (&fa)[3][NR]) {
         const int qd = 4 * c + g;
         const bool ok = 4 * c + 3 < NK || qd < NK;
         const int qr = ok ? qd : 0;
@@ -1324,15 +1324,41 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
         }
 #pragma unroll
         for (int rt = 0; rt < NR; ++rt) {
-          const uint4 ar = bD[((0 * NR + rt) * DB::NK + c) * 64 + lane];
-          const uint4 as = bD[((1 * NR + rt) * DB::NK + c) * 64 + lane];
-          const uint4 at = bD[((2 * NR + rt) * DB::NK + c) * 64 + lane];
-          DGRTM_MF3(ar, urh, url, cp[rt]);
-          DGRTM_MF3(as, ush, usl, cp[rt]);
-          DGRTM_MF3(at, uth, utl, cp[rt]);
-          DGRTM_MF3(ar, ph, pl, w0[rt]);
-          DGRTM_MF3(as, ph, pl, w1[rt]);
-          DGRTM_MF3(at, ph, pl, w2[rt]);
+          DGRTM_MF3(fa[0][rt], urh, url, cp[rt]);
+          DGRTM_MF3(fa[1][rt], ush, usl, cp[rt]);
+          DGRTM_MF3(fa[2][rt], uth, utl, cp[rt]);
+          DGRTM_MF3(fa[0][rt], ph, pl, w0[rt]);
+          DGRTM_MF3(fa[1][rt], ph, pl, w1[rt]);
+          DGRTM_MF3(fa[2][rt], ph, pl, w2[rt]);
+        }
+      };
+      auto bload = [&](int c, uint4 (&fa)[3][NR]) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int rt = 0; rt < NR; ++rt) fa[j][rt] = bD[((j * NR + rt) * DB::NK + c) * 64 + lane];
+      };
+      uint4 fa[3][NR];
+      if constexpr (OPS_LDS != 1) {
+        // fragments through the caches: two register buffers, as in the FP32 form
+        uint4 fb[3][NR];
+        bload(0, fa);
+        for (int c = 0; c < DB::NK; c += 2) {
+          __builtin_amdgcn_sched_barrier(0);
+          bload(min(c + 1, DB::NK - 1), fb);
+          __builtin_amdgcn_sched_barrier(0);
+          bchunk(c, fa);
+          __builtin_amdgcn_sched_barrier(0);
+          bload(min(c + 2, DB::NK - 1), fa);
+          __builtin_amdgcn_sched_barrier(0);
+          if (c + 1 < DB::NK) bchunk(c + 1, fb);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+#pragma unroll VU
+        for (int c = 0; c < DB::NK; ++c) {
+          bload(c, fa);
+          bchunk(c, fa);
         }
       }
     }
