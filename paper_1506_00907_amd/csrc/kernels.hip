@@ -1370,31 +1370,30 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     FaceCtx fcs[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) fcs[f] = face_ctx_of<N>(a, sl, f, gg, nbv[f], cdv[f]);
-    // the neighbour's traces at this lane's face nodes (the FP32 form loads all faces in one batch)
-    auto nbtrace = [&](const FaceCtx &fc, int cc, float &p_, float &v_) {
+    // the neighbour's traces at face node s of face fc (all faces' in one batch, in both forms)
+    auto nbnode = [&](const FaceCtx &fc, int s, float &p_, float &v_) {
       const bool inner = fc.nb >= 0;
+      const int sidx = min(s, Nfp - 1);
       // the face-node map in LDS: fc.tab points into the global copy at the same offset
       const int8_t *tab = stab + (fc.tab - a.nbr_index);
-      const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::TRF +
-                         tab[inner ? min(4 * cc + g, Nfp - 1) : 0];
+      const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::TRF + tab[inner ? sidx : 0];
       p_ = inner ? nbt[0] : 0.0f;
       v_ = inner ? nbt[Dm::TRC] : 0.0f;
       if constexpr (REPLAY) {
         if (fc.rep_b >= 0) {   // a replayed boundary face: the recorded run, own node order
           const float *row = replay_row<N>(a, sl, lev, m, fc.rep_b);
-          const int sidx = min(4 * cc + g, Nfp - 1);
           p_ = row[sidx];
           v_ = row[Dm::FS + sidx];
         }
       }
     };
-    float tpa[4][FC], tva[4][FC];
-    if constexpr (PREC == 0) {
+    // FP32: lane (e, g) takes face node 4 cc + g; split-BF16: face nodes 16 cc + 4 g + v
+    constexpr int TPN = PREC ? DB::FC * 4 : FC;
+    float tpa[4][TPN], tva[4][TPN];
 #pragma unroll
-      for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < 4; ++f)
 #pragma unroll
-        for (int cc = 0; cc < FC; ++cc) nbtrace(fcs[f], cc, tpa[f][cc], tva[f][cc]);
-    }
+      for (int i = 0; i < TPN; ++i) nbnode(fcs[f], PREC ? 16 * (i >> 2) + 4 * g + (i & 3) : 4 * i + g, tpa[f][i], tva[f][i]);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       const FaceCtx &fc = fcs[f];
@@ -1402,8 +1401,8 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
       // boundary states without branches (cP = 1 rigid wall, -1 free surface, 0 otherwise; 0 on
       // every face when the boundary faces are replayed)
       const float cP = REPLAY ? 0.0f : (fc.nb == -1 ? 1.0f : (fc.nb == -3 ? -1.0f : 0.0f));
-      float (&tp)[FC] = tpa[f];
-      float (&tv)[FC] = tva[f];
+      const float(&tp)[TPN] = tpa[f];
+      const float(&tv)[TPN] = tva[f];
       v4f G[NR];
 #pragma unroll
       for (int rt = 0; rt < NR; ++rt) G[rt] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1434,8 +1433,6 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
             G[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, Pv[cc], G[rt], 0, 0, 0);
           }
       } else {
-        const bool inner = fc.nb >= 0;
-        const int8_t *tab = stab + (fc.tab - a.nbr_index);
 #pragma unroll
         for (int cc = 0; cc < DB::FC; ++cc) {   // lane (e, g) takes face nodes 16 cc + 4 g + v
           v4s pph, ppl, pvh, pvl;
@@ -1445,16 +1442,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
             const bool sv = 16 * cc + 12 + v < Nfp || s < Nfp;
             const int node = sel4(g, T.fmask[f][min(16 * cc + v, Nfp - 1)], T.fmask[f][min(16 * cc + 4 + v, Nfp - 1)],
                                   T.fmask[f][min(16 * cc + 8 + v, Nfp - 1)], T.fmask[f][min(16 * cc + 12 + v, Nfp - 1)]);
-            const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::TRF +
-                               tab[inner ? min(s, Nfp - 1) : 0];
-            float tps = inner ? nbt[0] : 0.0f, tvs = inner ? nbt[Dm::TRC] : 0.0f;
-            if constexpr (REPLAY) {
-              if (fc.rep_b >= 0) {
-                const float *row = replay_row<N>(a, sl, lev, m, fc.rep_b);
-                tps = row[min(s, Nfp - 1)];
-                tvs = row[Dm::FS + min(s, Nfp - 1)];
-              }
-            }
+            const float tps = tp[4 * cc + v], tvs = tv[4 * cc + v];
             const float pm = q_t[lqix<N>(0, node, e)];
             const float nvm = fc.nx * q_t[lqix<N>(1, node, e)] + fc.ny * q_t[lqix<N>(2, node, e)] +
                               fc.nz * q_t[lqix<N>(3, node, e)];
