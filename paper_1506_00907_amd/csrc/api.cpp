@@ -896,6 +896,24 @@ static dgrtm_status begin_replay_segment(dgrtm_shot sh, int64_t gb) {
   sh->g0 = gb;
   sh->g1 = gb + 1;
   sh->g = gb;
+  if (gb > 0) {
+    // The segment's two history rows per level are the r-_S rows of its first own step's two
+    // predecessors, which the previous segment (the previous global step) recorded as its last
+    // two rows: level l's rows 2^(l-1) and 2^(l-1) + 1 move to rows 0 and 1, one after the other
+    // (at l = 1 the second source row is the first destination row's successor).
+    const int Np = m->ref.Np;
+    for (int l = 1; l <= h.L; ++l) {
+      const int64_t P = level_size_h(h, l);
+      if (P == 0) continue;
+      const int64_t row = (int64_t)Np * P, n = (int64_t)1 << (l - 1);
+      float *base = sh->seg_r + sh->seg_r_off[l - 1];
+      for (int i = 0; i < 2; ++i)
+        HIPCHK(hipMemcpyAsync(base + i * row, base + (n + i) * row, (size_t)row * sizeof(float),
+                              hipMemcpyDeviceToDevice, m->stream));
+    }
+    sh->ph = DGRTM_PHASE_RECOMPUTE;
+    return DGRTM_OK;
+  }
   SegInitArgs si;
   std::memset(&si, 0, sizeof(si));
   si.ring = sh->S.ring;

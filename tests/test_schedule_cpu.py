@@ -372,10 +372,20 @@ def test_boundary_replay_schedule(fake, mesh):
             lv = lev[act]
             m = n // 2 ** (L - lv)
             assert np.all(m >= (gb << (lv - 1))) and np.all(m < ((gb + 1) << (lv - 1)))
+    # the first segment's history rows come from the extrapolated start history; every later
+    # segment's are the previous segment's last two rows, moved to the front by two device copies
+    # per level before the segment's first source-field launch
     inits = log[log[:, 0] == R_SEG_INIT]
-    assert len(inits) == NG and np.all(inits[:, 1] == 1)
-    for gb, r in enumerate(inits):
-        assert [int(r[3 + l]) for l in range(L)] == [gb << l for l in range(L)]
+    assert len(inits) == 1 and inits[0, 1] == 1 and [int(inits[0, 3 + l]) for l in range(L)] == [0] * L
+    rows = np.flatnonzero(log[:, 0] == R_STEP)
+    nonempty = len(np.unique(mesh.level))
+    for gb in range(1, NG):
+        first_S = rows[3 + 2 * gb * nl]
+        last_R = rows[3 + 2 * gb * nl - 1]
+        between = log[last_R + 1:first_S]
+        assert log[first_S, 1] == M_REPLAY_SEG and log[last_R, 1] == M_IMAGE
+        assert np.sum((between[:, 0] == R_COPY) & (between[:, 1] == D2D)) == 2 * nonempty
+        assert not np.any(between[:, 0] == R_SEG_INIT)
 
 
 def test_batched_shots_see_their_solo_schedule(fake, mesh):
