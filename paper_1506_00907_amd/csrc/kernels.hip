@@ -1502,40 +1502,49 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
   }
 }
 
+// Own-step traces of a whole field's state (at the start of a run or after a restore), as the step
+// kernels write them: one wavefront per 16-element tile, lane (e, g) writes face g of element e as
+// 16-byte stores of its p and n.v runs (the padding after the last face node gets zeros), reading
+// the face nodes of the state per lane.
 template <int N>
 __global__ __launch_bounds__(256) void trace_init_kernel(const TraceInitArgs a) {
   constexpr Tab<N> T{};
-  constexpr int Np = Tab<N>::Np, Nfp = Tab<N>::Nfp, F = 4 * Nfp;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.Ktot) return;
+  constexpr int Np = Tab<N>::Np, Nfp = Tab<N>::Nfp, NQ4 = node_quads(Np);
+  constexpr int FS = Dims<N>::FS, TRC = Dims<N>::TRC, TRS = Dims<N>::TRS, TRF = Dims<N>::TRF;
+  const int lane = threadIdx.x & 63;
+  const int e = lane & 15, g = lane >> 4;
   const int64_t K = a.Ktot;
+  const int64_t k = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + e;
+  if (k >= K) return;
   if (!(a.eflag[k] & 1)) return;
   const int lev = level_of(a.lev_begin, a.L, k);
   const int64_t m = a.tau >> (a.L - lev);
-  constexpr int FS = Dims<N>::FS, TRC = Dims<N>::TRC, TRS = Dims<N>::TRS;
-  float *tr = a.tr + (m & 1) * (int64_t)TRS * K;
-  float g[9];
+  float gv[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = a.geo[tix(kGeo, i, k)];
+  for (int i = 0; i < 9; ++i) gv[i] = a.geo[tix(kGeo, i, k)];
+  // outward normal of face g (the step kernels' face contexts compute it the same way)
+  float nx = g == 0 ? -gv[6] : (g == 1 ? -gv[3] : (g == 2 ? gv[0] + gv[3] + gv[6] : -gv[0]));
+  float ny = g == 0 ? -gv[7] : (g == 1 ? -gv[4] : (g == 2 ? gv[1] + gv[4] + gv[7] : -gv[1]));
+  float nz = g == 0 ? -gv[8] : (g == 1 ? -gv[5] : (g == 2 ? gv[2] + gv[5] + gv[8] : -gv[2]));
+  const float Fs = sqrtf(nx * nx + ny * ny + nz * nz);
+  const float inv = 1.0f / Fs;
+  nx *= inv; ny *= inv; nz *= inv;
+  float *tr = a.tr + (m & 1) * (int64_t)TRS * K + k * TRS + g * TRF;
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    float nx, ny, nz;
-    if (f == 0) { nx = -g[6]; ny = -g[7]; nz = -g[8]; }
-    else if (f == 1) { nx = -g[3]; ny = -g[4]; nz = -g[5]; }
-    else if (f == 2) { nx = g[0] + g[3] + g[6]; ny = g[1] + g[4] + g[7]; nz = g[2] + g[5] + g[8]; }
-    else { nx = -g[0]; ny = -g[1]; nz = -g[2]; }
-    const float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
-    nx *= inv; ny *= inv; nz *= inv;
+  for (int j = 0; j < FS / 4; ++j) {
+    float p[4], v[4];
 #pragma unroll
-    for (int i = 0; i < Nfp; ++i) {
-      const int node = T.fmask[f][i];
-      const float p = a.q[qix(node_quads(Np), 0, node, k)];
-      const float vx = a.q[qix(node_quads(Np), 1, node, k)];
-      const float vy = a.q[qix(node_quads(Np), 2, node, k)];
-      const float vz = a.q[qix(node_quads(Np), 3, node, k)];
-      tr[(int64_t)k * TRS + f * Dims<N>::TRF + i] = p;
-      tr[(int64_t)k * TRS + f * Dims<N>::TRF + TRC + i] = nx * vx + ny * vy + nz * vz;
+    for (int u = 0; u < 4; ++u) {
+      const int s = 4 * j + u;
+      p[u] = v[u] = 0.0f;
+      if (s < Nfp) {
+        const int node = sel4(g, T.fmask[0][s], T.fmask[1][s], T.fmask[2][s], T.fmask[3][s]);
+        p[u] = a.q[qix(NQ4, 0, node, k)];
+        v[u] = nx * a.q[qix(NQ4, 1, node, k)] + ny * a.q[qix(NQ4, 2, node, k)] + nz * a.q[qix(NQ4, 3, node, k)];
+      }
     }
+    *reinterpret_cast<float4 *>(tr + 4 * j) = float4{p[0], p[1], p[2], p[3]};
+    *reinterpret_cast<float4 *>(tr + TRC + 4 * j) = float4{v[0], v[1], v[2], v[3]};
   }
 }
 
@@ -1863,7 +1872,7 @@ hipError_t launch_step(int N, const StepArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_trace_init(int N, const TraceInitArgs &a, hipStream_t st) {
-  const dim3 grid(blocks_for(a.Ktot, 256)), block(256);
+  const dim3 grid(blocks_for(a.Ktot, 64)), block(256);   // four 16-element tiles per work-group
   switch (N) {
     case 1: hipLaunchKernelGGL(trace_init_kernel<1>, grid, block, 0, st, a); break;
     case 2: hipLaunchKernelGGL(trace_init_kernel<2>, grid, block, 0, st, a); break;
