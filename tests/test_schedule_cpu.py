@@ -303,6 +303,21 @@ def test_adjoint_segments_and_image_pairing(fake, mesh, g_image_start):
         rec = [i for i, o in enumerate(order) if o[0] == M_RECORD_SEG and g0 * nl <= o[1] < g1 * nl]
         assert sel and rec and max(rec) < min(sel)
         assert [order[i][1] for i in sel] == list(range((NG - g1) * nl, (NG - max(g0, g_image_start)) * nl))
+    # each segment starts from its checkpoint: the state and the two newest rhs of every level
+    # come back by device copies, then its traces and its segment history, before its first
+    # recompute launch
+    steps_at = np.flatnonzero(log[:, 0] == R_STEP)
+    nonempty = len(np.unique(mesh.level))
+    prev = -1
+    for c in cs:
+        first = next(i for i in steps_at if log[i, 1] == M_RECORD_SEG and log[i, 6] == c * Cc * nl)
+        blk = log[prev + 1:first]
+        kinds = blk[:, 0]
+        assert np.sum((kinds == R_COPY) & (blk[:, 1] == D2D)) == 1 + 2 * nonempty, f"segment {c}"
+        assert np.sum(kinds == R_TRACE_INIT) == 1 and np.sum(kinds == R_SEG_INIT) == 1
+        ti = blk[kinds == R_TRACE_INIT][0]
+        assert ti[2] == c * Cc * nl, "traces of the restored state at the segment's first local step"
+        prev = max(i for i in steps_at if log[i, 1] == M_IMAGE and log[i, 8] == c * Cc) if c != cs[-1] else first
     # active sets of the backward run are the oracle's
     ev = oracle_ev_sequence(lev, L, n_img)
     for n, row in enumerate(img):
