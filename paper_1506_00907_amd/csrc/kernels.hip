@@ -1148,6 +1148,19 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     copy_block<kGeo>(a.geo + tix(kGeo, 0, t * 16), lg, lane);
   };
   if (tile < ntiles) issue(tile);
+  // neighbour entries and codes of a tile's faces: with the operators in LDS they are loaded with
+  // the tile's copies (the face contexts need them before the volume terms), else at its top
+  int nbv[4], cdv[4];
+  auto load_nb = [&](int64_t t) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      nbv[f] = a.nbr[tix(4, f, t * 16 + e)];
+      cdv[f] = a.ncode[tix(4, f, t * 16 + e)];
+    }
+  };
+  if constexpr (OPS_LDS == 1) {
+    if (tile < ntiles) load_nb(tile);
+  }
   const float *ops = PREC ? reinterpret_cast<const float *>(a.ops_bf16) : a.ops;
   const float *lift = ops + DW;
   if constexpr (OPS_LDS == 1) {
@@ -1183,13 +1196,7 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     const int64_t k = tile * 16 + e;
     uint32_t vnn = 0u;   // the tile after the next (counter value), read at the end of this tile
     if (dyn && nxt < ntiles && lane == 0) vnn = atomicAdd(ctr, 1u);
-    // neighbour entries and codes of the tile's faces: they land while the volume terms run
-    int nbv[4], cdv[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      nbv[f] = a.nbr[tix(4, f, k)];
-      cdv[f] = a.ncode[tix(4, f, k)];
-    }
+    if constexpr (OPS_LDS != 1) load_nb(tile);   // (they land while the volume terms run)
     const float *__restrict__ fD = ops + opaque0;                       // [3][NR][NK][64]
     const float *__restrict__ fL = lift + opaque0;                      // [NR][4*FC][64]
     const uint4 *__restrict__ bD = reinterpret_cast<const uint4 *>(ops) + opaque0;          // split-BF16
@@ -1206,6 +1213,42 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
                 tz = gg[8];
     const float rc2 = gg[9], irho = gg[10];
 
+    // The faces' contexts and their neighbour traces (all faces' in one batch, in both forms).
+    // With the operators in LDS they come before the volume terms, which then wait on no global
+    // load, so the gathers land while they run; with the volume fragments read through the caches
+    // they come after (a gather issued before would be waited for by the first fragment wait).
+    float nfx[4], nfy[4], nfz[4];
+    FaceCtx fcs[4];
+    // FP32: lane (e, g) takes face node 4 cc + g; split-BF16: face nodes 16 cc + 4 g + v
+    constexpr int TPN = PREC ? DB::FC * 4 : FC;
+    float tpa[4][TPN], tva[4][TPN];
+    auto faces = [&]() {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) fcs[f] = face_ctx_of<N>(a, sl, f, gg, nbv[f], cdv[f]);
+      // the neighbour's traces at face node s of face fc
+      auto nbnode = [&](const FaceCtx &fc, int s, float &p_, float &v_) {
+        const bool inner = fc.nb >= 0;
+        const int sidx = min(s, Nfp - 1);
+        // the face-node map in LDS: fc.tab points into the global copy at the same offset
+        const int8_t *tab = stab + (fc.tab - a.nbr_index);
+        const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::TRF + tab[inner ? sidx : 0];
+        p_ = inner ? nbt[0] : 0.0f;
+        v_ = inner ? nbt[Dm::TRC] : 0.0f;
+        if constexpr (REPLAY) {
+          if (fc.rep_b >= 0) {   // a replayed boundary face: the recorded run, own node order
+            const float *row = replay_row<N>(a, sl, lev, m, fc.rep_b);
+            p_ = row[sidx];
+            v_ = row[Dm::FS + sidx];
+          }
+        }
+      };
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int i = 0; i < TPN; ++i)
+          nbnode(fcs[f], PREC ? 16 * (i >> 2) + 4 * g + (i & 3) : 4 * i + g, tpa[f][i], tva[f][i]);
+    };
+    if constexpr (OPS_LDS == 1) faces();
     // ---- volume: Cp = sum_j D_j U_j and W_j = D_j p
     v4f cp[NR], w0[NR], w1[NR], w2[NR];
 #pragma unroll
@@ -1365,35 +1408,9 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     v4f rp[NR], rvx[NR], rvy[NR], rvz[NR];
     volume_to_rhs<NR>(gg, cp, w0, w1, w2, rp, rvx, rvy, rvz);
 
+    if constexpr (OPS_LDS != 1) faces();
+
     // ---- surface: rp -= LIFT Pp (accumulated by the MFMA with -Pp), G_f = LIFT_f Pv, rv -= n_f G_f
-    float nfx[4], nfy[4], nfz[4];
-    FaceCtx fcs[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) fcs[f] = face_ctx_of<N>(a, sl, f, gg, nbv[f], cdv[f]);
-    // the neighbour's traces at face node s of face fc (all faces' in one batch, in both forms)
-    auto nbnode = [&](const FaceCtx &fc, int s, float &p_, float &v_) {
-      const bool inner = fc.nb >= 0;
-      const int sidx = min(s, Nfp - 1);
-      // the face-node map in LDS: fc.tab points into the global copy at the same offset
-      const int8_t *tab = stab + (fc.tab - a.nbr_index);
-      const float *nbt = fc.trp + (int64_t)(inner ? fc.nb : 0) * Dm::TRS + fc.f2 * Dm::TRF + tab[inner ? sidx : 0];
-      p_ = inner ? nbt[0] : 0.0f;
-      v_ = inner ? nbt[Dm::TRC] : 0.0f;
-      if constexpr (REPLAY) {
-        if (fc.rep_b >= 0) {   // a replayed boundary face: the recorded run, own node order
-          const float *row = replay_row<N>(a, sl, lev, m, fc.rep_b);
-          p_ = row[sidx];
-          v_ = row[Dm::FS + sidx];
-        }
-      }
-    };
-    // FP32: lane (e, g) takes face node 4 cc + g; split-BF16: face nodes 16 cc + 4 g + v
-    constexpr int TPN = PREC ? DB::FC * 4 : FC;
-    float tpa[4][TPN], tva[4][TPN];
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-      for (int i = 0; i < TPN; ++i) nbnode(fcs[f], PREC ? 16 * (i >> 2) + 4 * g + (i & 3) : 4 * i + g, tpa[f][i], tva[f][i]);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       const FaceCtx &fc = fcs[f];
@@ -1484,7 +1501,10 @@ __global__ __launch_bounds__(256) void step_kernel_lowreg(const StepArgs a) {
     // every LDS read of this tile is done: the next tile's copies may land
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    if (nxt < ntiles) issue(nxt);
+    if (nxt < ntiles) {
+      issue(nxt);
+      if constexpr (OPS_LDS == 1) load_nb(nxt);
+    }
     tile = nxt;
     nxt = nn;
   }
